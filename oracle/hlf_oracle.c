@@ -1,0 +1,144 @@
+/* Plain C oracle of the FS2D HLF stage-2 enumeration -- TEST INFRASTRUCTURE.
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg load
+ * this file's shared object.  It shares nothing with the HIP library.
+ *
+ * Every function is the direct per-index definition, with OpenMP over the
+ * index range and no other restructuring:
+ *
+ *   z_i = l XOR ( XOR over k < r with bit k of g(i) set of B_k ),
+ *   g(i) = i XOR (i >> 1),
+ *
+ * which is the paper's second stage (Section 2, Eq. (3) restricted to the
+ * pivot inputs, followed by the final CNOT layer with z^a = l), traversed in
+ * Gray order.  Vectors are W little-endian 64-bit words; bit j of the vector
+ * is z_{j+1}.
+ *
+ * Hash of one solution (a project convention): h_0 = 0,
+ * h_{w+1} = mix13(h_w ^ z_w ^ GAMMA), h(z) = h_W; the hash of a set is the sum
+ * of h(z) mod 2^64.  mix13 is the output function of Vigna's public-domain
+ * SplitMix64 (Stafford's Mix13); GAMMA is SplitMix64's increment.
+ *
+ * Parity pins: tests compare these functions with the Python oracle on small
+ * ranges and with closed forms (per-qubit counts, full-rank identity hash).
+ */
+#include <stdint.h>
+#include <string.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define GAMMA 0x9E3779B97F4A7C15ULL
+
+static uint64_t mix13(uint64_t x) {
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ULL;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBULL;
+    x ^= x >> 31;
+    return x;
+}
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+uint64_t oracle_mix13(uint64_t x) { return mix13(x); }
+
+/* z_i into z[0..W-1] by the direct definition. */
+static void solution_at(const uint64_t *basis, int r, int W, const uint64_t *shift,
+                        uint64_t i, uint64_t *z) {
+    uint64_t g = i ^ (i >> 1);
+    for (int w = 0; w < W; ++w) z[w] = shift[w];
+    for (int k = 0; k < r; ++k) {
+        if ((g >> k) & 1ULL) {
+            for (int w = 0; w < W; ++w) z[w] ^= basis[(size_t)k * W + w];
+        }
+    }
+}
+
+static uint64_t hash_words(const uint64_t *z, int W) {
+    uint64_t h = 0;
+    for (int w = 0; w < W; ++w) h = mix13(h ^ z[w] ^ GAMMA);
+    return h;
+}
+
+/* out[(i - begin) * W + w] = word w of z_i, i in [begin, begin + count). */
+int oracle_enumerate(const uint64_t *basis, int r, int W, const uint64_t *shift,
+                     uint64_t begin, uint64_t count, uint64_t *out) {
+    if (r < 0 || r > 62 || W < 1 || W > 16) return -1;
+    if (begin > (1ULL << r) || count > (1ULL << r) - begin) return -3;
+    int64_t cnt = (int64_t)count;
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < cnt; ++t) {
+        solution_at(basis, r, W, shift, begin + (uint64_t)t, out + (size_t)t * W);
+    }
+    return 0;
+}
+
+/* counts[j] = #solutions with bit j set (j < n); *hash = sum of h(z);
+ * xorfold[w] = XOR of all solutions (may be NULL). */
+int oracle_reduce(const uint64_t *basis, int r, int W, int n, const uint64_t *shift,
+                  uint64_t begin, uint64_t count, uint64_t *counts, uint64_t *hash,
+                  uint64_t *xorfold) {
+    if (r < 0 || r > 62 || W < 1 || W > 16 || n < 1 || n > 64 * W) return -1;
+    if (begin > (1ULL << r) || count > (1ULL << r) - begin) return -3;
+    int64_t cnt = (int64_t)count;
+    int nt = oracle_threads();
+    uint64_t *part_counts = (uint64_t *)calloc((size_t)nt * n, sizeof(uint64_t));
+    uint64_t *part_hash = (uint64_t *)calloc((size_t)nt, sizeof(uint64_t));
+    uint64_t *part_xor = (uint64_t *)calloc((size_t)nt * W, sizeof(uint64_t));
+    if (!part_counts || !part_hash || !part_xor) {
+        free(part_counts); free(part_hash); free(part_xor);
+        return -4;
+    }
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+        int tid = omp_get_thread_num();
+#else
+        int tid = 0;
+#endif
+        uint64_t z[16];
+        uint64_t *pc = part_counts + (size_t)tid * n;
+        uint64_t *px = part_xor + (size_t)tid * W;
+        uint64_t ph = 0;
+#pragma omp for schedule(static)
+        for (int64_t t = 0; t < cnt; ++t) {
+            solution_at(basis, r, W, shift, begin + (uint64_t)t, z);
+            for (int j = 0; j < n; ++j) pc[j] += (z[j >> 6] >> (j & 63)) & 1ULL;
+            ph += hash_words(z, W);
+            for (int w = 0; w < W; ++w) px[w] ^= z[w];
+        }
+        part_hash[tid] = ph;
+    }
+    for (int j = 0; j < n; ++j) counts[j] = 0;
+    *hash = 0;
+    if (xorfold) for (int w = 0; w < W; ++w) xorfold[w] = 0;
+    for (int t = 0; t < nt; ++t) {
+        for (int j = 0; j < n; ++j) counts[j] += part_counts[(size_t)t * n + j];
+        *hash += part_hash[t];
+        if (xorfold) for (int w = 0; w < W; ++w) xorfold[w] ^= part_xor[(size_t)t * W + w];
+    }
+    free(part_counts); free(part_hash); free(part_xor);
+    return 0;
+}
+
+/* Sum of h(z) over every 64-bit value z in [lo, hi): the hash of the whole
+ * solution set {0,1}^n of a full-rank instance (r = n <= 62), independent of
+ * the basis and of the enumeration order. */
+uint64_t oracle_identity_hash(uint64_t lo, uint64_t hi) {
+    int64_t cnt = (int64_t)(hi - lo);
+    uint64_t total = 0;
+#pragma omp parallel for schedule(static) reduction(+ : total)
+    for (int64_t t = 0; t < cnt; ++t) {
+        uint64_t z = lo + (uint64_t)t;
+        total += mix13(z ^ GAMMA);
+    }
+    return total;
+}
