@@ -1,0 +1,184 @@
+/* hlf.h -- C ABI of the MI355X (gfx950) FS2D HLF library, libhlf.so.
+ *
+ * The library solves the full-sampling 2D hidden linear function problem
+ * (paper: "High-performance parallel classical scheme for simulating shallow
+ * quantum circuits", Sections 1-2): given an n x n symmetric binary matrix A,
+ * produce every z in {0,1}^n with q(x) = 2 z^T x (mod 4) for all x in Ker(A),
+ * where q(x) = x^T A x mod 4 over the integers.  The solution set is the
+ * affine space l XOR Col(A) with 2^r members, r = rank of A over GF(2)
+ * (Section 2).
+ *
+ * Stage 1 (the paper's CLA module, Section 2 tasks (1)-(4)) is hlf_factor.
+ * Stage 2 (the paper's classical parallel circuit, Section 2, Eqs. (1)-(3)) is
+ * hlf_enumerate / hlf_enumerate_reduce, which traverse the 2^r inputs R^(r);
+ * hlf_sample draws single uniform solutions, the output distribution of the
+ * quantum circuit (Appendix A).
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions (shared by every entry point)
+ * ---------------------------------------------------------------------------
+ * Bit vectors.  A vector of n bits is W = ceil(n/64) little-endian uint64
+ *   words; bit j (word j/64, bit j%64) is z_{j+1}, i.e. vertex j (0-based).
+ *   Bits at positions >= n ("pad bits") are zero in every output and must be
+ *   zero in every input.
+ * Packed matrix.  rows[i*W + w] holds word w of row i of A: bit j of row i is
+ *   A_ij.
+ * Pivots P.  The ascending pivot columns of the reduced row echelon form of A
+ *   over GF(2): the lexicographically first maximal independent column set
+ *   (task (1)).  It does not depend on the elimination order.
+ * Basis.  B_k = column p_k of A (= row p_k, A symmetric), k = 0..r-1.
+ * Kernel basis.  For the free columns f (not in P), ascending: k_f has a 1 at
+ *   f, 0 at every other free column and RREF[k][f] at pivot p_k (task (2)).
+ * Shift l.  The unique solution with l_p = 0 for all p in P; l_f = q(k_f)/2
+ *   for every free column f (tasks (3)-(4)).
+ * Order.  Solution number i, 0 <= i < 2^r, is
+ *       z_i = l XOR ( XOR_{k : bit k of g(i) is set} B_k ),  g(i) = i ^ (i>>1),
+ *   the Gray-code traversal of R^(r) = (R_{p_1}..R_{p_r}); successive
+ *   solutions differ by B_{ctz(i)}.
+ * Hash.  h(z) = h_W with h_0 = 0, h_{w+1} = mix13(h_w ^ z_w ^ 0x9E3779B97F4A7C15),
+ *   where mix13(x): x ^= x>>30; x *= 0xBF58476D1CE4E5B9; x ^= x>>27;
+ *   x *= 0x94D049BB133111EB; x ^= x>>31 (all mod 2^64) -- the output function
+ *   of SplitMix64 (Stafford's Mix13).  The hash of a set of solutions is the
+ *   sum of h(z) mod 2^64, so it does not depend on the order and is additive
+ *   over disjoint index ranges.
+ * Sampling coefficients.  Word w (< R64 = ceil(r/64)) of the coefficient vector
+ *   of sample s is the SplitMix64 output number s*R64 + w for the state that
+ *   starts at `seed`: mix13(seed + (s*R64 + w + 1) * 0x9E3779B97F4A7C15); bits
+ *   at positions >= r are cleared.  Sample s is l XOR (XOR_{bit k of c_s} B_k).
+ *
+ * Memory and streams.  Every pointer named *_dev is caller-owned device memory
+ *   on the current HIP device; the library does not allocate, free or keep any
+ *   of it.  Every call is asynchronous on the caller's stream and returns once
+ *   the work is enqueued.  Calls on different streams are independent; calls
+ *   that write the same buffers must be ordered by the caller.
+ *
+ * Errors.  A host-detectable error (NULL pointer, n out of range, bad
+ *   word_bits or flags) is returned at once and nothing is enqueued.
+ *   Device-detectable errors are written to the factor record's status word:
+ *   HLF_ENOTSYM for a matrix that is not symmetric or has nonzero pad bits,
+ *   HLF_ERANGE for an index range outside [0, 2^r) or r > 62 in enumerate.
+ *   Every later kernel that reads a record whose status is not HLF_OK does
+ *   nothing (it writes no output), so a caller can enqueue a whole pipeline
+ *   and check `status` once after synchronising.  A failed launch returns
+ *   HLF_EDEVICE.
+ */
+#ifndef HLF_H
+#define HLF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hlf_status {
+    HLF_OK = 0,
+    HLF_EINVAL = -1,      /* bad argument (host-detected)                       */
+    HLF_ENOTSYM = -2,     /* A not symmetric / not 0-1 / nonzero pad bits        */
+    HLF_ERANGE = -3,      /* index range outside [0, 2^r), or r > 62            */
+    HLF_ENOMEM = -4,      /* a capacity limit was exceeded                       */
+    HLF_EDEVICE = -5,     /* a HIP call failed                                   */
+    HLF_ECANCELLED = -6,  /* work was cancelled by the host                      */
+    HLF_EINTERNAL = -7    /* an internal invariant failed (q odd on Ker(A))      */
+} hlf_status;
+
+#define HLF_MAX_N 1024          /* largest n accepted by hlf_factor             */
+#define HLF_MAX_WORDS 16        /* ceil(HLF_MAX_N / 64)                          */
+#define HLF_MAX_ENUM_RANK 62    /* largest r for enumerate / reduce              */
+
+/* Flags of hlf_enumerate_reduce. */
+#define HLF_ACCUMULATE 1u       /* add into counts/hash/xorfold instead of overwriting */
+
+/* Flags of hlf_factor_ex. */
+#define HLF_FACTOR_WORKGROUP 1u /* force the workgroup (LDS) variant for any n   */
+
+/* Device-resident factor record (paper Section 2, tasks (1)-(4)).  The host
+ * fills n and words and points the remaining members at caller-owned device
+ * buffers of the stated sizes; hlf_factor writes them.                         */
+typedef struct hlf_factors {
+    int32_t n;          /* number of vertices, 1 .. HLF_MAX_N                      */
+    int32_t words;      /* W = ceil(n / 64)                                        */
+    int32_t *status;    /* dev [1]: hlf_status of the record                       */
+    int32_t *rank;      /* dev [1]: r                                              */
+    int32_t *pivots;    /* dev [n]: p_0 < ... < p_{r-1}; entries r..n-1 are -1     */
+    uint64_t *basis;    /* dev [n*W]: rows 0..r-1 hold B_k; other rows untouched   */
+    uint64_t *shift;    /* dev [W]: l                                              */
+    uint64_t *kernel;   /* dev [n*W] or NULL: rows 0..n-r-1 hold k_f (f ascending) */
+} hlf_factors;
+
+/* Library version, (major << 16) | minor. */
+int32_t hlf_version(void);
+
+/* Human-readable name of a status code (static storage). */
+const char *hlf_status_string(int32_t status);
+
+/* ceil(n / 64): words per packed row or vector. */
+int32_t hlf_words_for(int32_t n);
+
+/* Pack and validate a dense matrix (the input of Section 1).
+ *   A_dev      dev uint8 [n*n], row-major, entries 0 or 1.
+ *   n          1 .. HLF_MAX_N.
+ *   rows_dev   dev uint64 [n*W] output, packed rows (pad bits zero).
+ *   status_dev dev int32 [1] output: HLF_OK, or HLF_ENOTSYM if A is not
+ *              symmetric or holds a value other than 0 and 1.
+ * Returns HLF_EINVAL for NULL pointers or n out of range.                       */
+hlf_status hlf_pack_dense(const uint8_t *A_dev, int32_t n, uint64_t *rows_dev,
+                          int32_t *status_dev, hipStream_t stream);
+
+/* Stage 1, the CLA module (Section 2, tasks (1)-(4)): GF(2) Gauss-Jordan
+ * elimination of the packed rows giving r and P, the Ker(A) basis, q(k_f) and
+ * the canonical shift l, and the column-space basis B_k.
+ *   rows_dev   dev uint64 [n*W], packed A (read only).
+ *   f          host pointer to a record whose n, words and buffers are set;
+ *              f->kernel may be NULL.  The record is read at call time only.
+ * Writes f->status (HLF_OK, HLF_ENOTSYM, or HLF_EINTERNAL), f->rank,
+ * f->pivots, f->basis, f->shift and, if not NULL, f->kernel.  Any n up to
+ * HLF_MAX_N; n <= 192 runs one wavefront per instance, larger n one workgroup.
+ * Returns HLF_EINVAL for NULL pointers, n out of range or words != ceil(n/64). */
+hlf_status hlf_factor(const uint64_t *rows_dev, const hlf_factors *f, hipStream_t stream);
+
+/* hlf_factor with flags (HLF_FACTOR_WORKGROUP selects the workgroup variant
+ * for every n; the results are identical).                                     */
+hlf_status hlf_factor_ex(const uint64_t *rows_dev, const hlf_factors *f, uint32_t flags,
+                         hipStream_t stream);
+
+/* Stage 2, materialise (Section 2, the traversal of R^(r) through Eq. (3) and
+ * the final CNOT layer): out[i - begin] = z_i for i in [begin, begin + count).
+ *   word_bits  16, 32 or 64 when n <= word_bits <= 64: one uint16/uint32/uint64
+ *              per solution; or 64*W for any n: W uint64 words per solution.
+ *   out_dev    dev buffer of count * word_bits / 8 bytes; the fast path needs
+ *              16-byte alignment (any alignment is correct).
+ * Device errors: HLF_ERANGE in f->status if r > 62 or begin + count > 2^r
+ * (nothing is written).  count = 0 enqueues nothing and returns HLF_OK.
+ * Returns HLF_EINVAL for NULL pointers or word_bits not allowed for n.          */
+hlf_status hlf_enumerate(const hlf_factors *f, uint64_t begin, uint64_t count,
+                         int32_t word_bits, void *out_dev, hipStream_t stream);
+
+/* Stage 2, reduce: over the solutions z_i, i in [begin, begin + count),
+ *   counts_dev  dev uint64 [n]: counts[j] = number of solutions with bit j set;
+ *   hash_dev    dev uint64 [1]: sum of h(z_i) mod 2^64;
+ *   xorfold_dev dev uint64 [W] or NULL: XOR of all z_i.
+ * Outputs are overwritten, or added to (counts, hash: mod 2^64; xorfold: XOR)
+ * with HLF_ACCUMULATE, so disjoint ranges can be reduced one after another.
+ * Device errors as hlf_enumerate.  count = 0 with overwrite zeroes the outputs. */
+hlf_status hlf_enumerate_reduce(const hlf_factors *f, uint64_t begin, uint64_t count,
+                                uint32_t flags, uint64_t *counts_dev, uint64_t *hash_dev,
+                                uint64_t *xorfold_dev, hipStream_t stream);
+
+/* Uniform single solutions, as the quantum circuit outputs them (Section 1,
+ * Appendix A): out[s*W .. s*W+W-1] = l XOR (XOR_{bit k of c_s} B_k),
+ * s = 0 .. num-1.
+ *   seed       state of the SplitMix64 coefficient stream (see Conventions).
+ *   coeffs_dev NULL, or dev uint64 [num * ceil(r/64)]: explicit coefficient
+ *              vectors (bits >= r ignored), r being the rank in the record.
+ *   out_dev    dev uint64 [num * W].
+ * Works for any r (no 62-bit limit).  num = 0 enqueues nothing.                 */
+hlf_status hlf_sample(const hlf_factors *f, uint64_t seed, uint64_t num,
+                      const uint64_t *coeffs_dev, uint64_t *out_dev, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HLF_H */

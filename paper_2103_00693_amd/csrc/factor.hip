@@ -1,0 +1,471 @@
+// Stage 1 of the two-stage scheme (the paper's CLA module, Section 2,
+// tasks (1)-(4)) on gfx950:
+//   * pack_dense_kernel: dense 0/1 matrix -> packed uint64 rows, with the
+//     symmetry / 0-1 validation of the problem statement (Section 1);
+//   * factor_wave_kernel: one wavefront per instance for n <= 192; every
+//     lane keeps its rows in VGPRs, pivots are found with a ballot and the
+//     pivot row is broadcast with readlane -- no barriers in the elimination;
+//   * factor_workgroup_kernel: one workgroup per instance for n <= 1024, one
+//     row per thread in VGPRs, pivot choice by an LDS atomicMin over per-wave
+//     ballots, the pivot row broadcast through LDS.
+// Both variants produce the canonical record defined in hlf.h (the RREF is
+// unique, so the pivot rows chosen do not matter).
+#include "hlf_device.h"
+#include "hlf_internal.h"
+
+#include <climits>
+
+namespace hlf {
+namespace {
+
+// ---------------------------------------------------------------------------
+// A0: pack + validate.  One workgroup of 64*W threads; wave v packs rows
+// v, v + W, ... by ballot over 64 consecutive bytes, then checks A = A^T: for
+// column c, the ballot of bit c over the 64 rows held by wave v is word v of
+// column c, which must equal word v of row c.
+// ---------------------------------------------------------------------------
+template <int WMAX>
+__global__ __launch_bounds__(64 * WMAX) void pack_dense_kernel(const uint8_t *__restrict__ A, int n,
+                                                               int W, uint64_t *__restrict__ rows,
+                                                               int32_t *__restrict__ status) {
+    __shared__ uint64_t lds[64 * WMAX * WMAX];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int nwaves = blockDim.x >> 6;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+
+    int mybad = 0;
+    for (int i = wave; i < n; i += nwaves) {
+        const uint8_t *src = A + (size_t)i * n;
+        for (int w = 0; w < W; ++w) {
+            const int j = 64 * w + lane;
+            const uint8_t v = (j < n) ? src[j] : (uint8_t)0;
+            mybad |= (v > 1);
+            const uint64_t word = __ballot(v == 1);
+            if (lane == 0) lds[i * W + w] = word;
+        }
+    }
+    __syncthreads();
+
+    const int i = tid;
+    uint64_t row[WMAX];
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w) row[w] = (i < n && w < W) ? lds[i * W + w] : 0ull;
+#pragma unroll
+    for (int cw = 0; cw < WMAX; ++cw) {
+        if (cw >= W) break;
+        for (int cb = 0; cb < 64; ++cb) {
+            const int c = 64 * cw + cb;
+            if (c >= n) break;
+            const uint64_t col = __ballot((row[cw] >> cb) & 1ull);
+            if (col != lds[c * W + wave]) mybad = 1;
+        }
+    }
+    if (mybad) bad = 1;
+    __syncthreads();
+    for (int idx = tid; idx < n * W; idx += blockDim.x) rows[idx] = lds[idx];
+    if (tid == 0) *status = bad ? HLF_ENOTSYM : HLF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// A1-A4, wavefront variant: n <= 64*WMAX, WMAX in {1,2,3}.  Lane l holds rows
+// l, l+64, l+128 ("slots").  Launched with one 64-thread workgroup per
+// instance, so __syncthreads is a single-wave barrier.
+// ---------------------------------------------------------------------------
+template <int WMAX>
+struct WaveSmem {
+    uint64_t orig[64 * WMAX * WMAX];  // A, packed
+    uint64_t rref[64 * WMAX * WMAX];  // RREF row k at k*W
+    int piv[64 * WMAX];
+    int freec[64 * WMAX];
+    unsigned long long shiftw[WMAX];
+    int internal;
+};
+
+template <int WMAX>
+__device__ __forceinline__ void set_bit(uint64_t (&v)[WMAX], int pos) {
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w)
+        if (w == (pos >> 6)) v[w] |= 1ull << (pos & 63);
+}
+
+template <int WMAX>
+__device__ void factor_wave(const uint64_t *__restrict__ rows, int n, int W, const FactorOut &out,
+                            WaveSmem<WMAX> &sm) {
+    const int lane = lane_id();
+    for (int idx = lane; idx < n * W; idx += 64) sm.orig[idx] = rows[idx];
+    if (lane < WMAX) sm.shiftw[lane] = 0;
+    if (lane == 0) sm.internal = 0;
+    __syncthreads();
+
+    uint64_t row[WMAX][WMAX];
+    bool used[WMAX];
+    int rk[WMAX];
+#pragma unroll
+    for (int s = 0; s < WMAX; ++s) {
+        const int i = s * 64 + lane;
+#pragma unroll
+        for (int w = 0; w < WMAX; ++w) row[s][w] = (i < n && w < W) ? sm.orig[i * W + w] : 0ull;
+        used[s] = false;
+        rk[s] = -1;
+    }
+
+    // Validation: pad bits zero, A = A^T (ballot over slot s = word s of a column).
+    bool bad = false;
+    const uint64_t lm = last_word_mask(n);
+#pragma unroll
+    for (int s = 0; s < WMAX; ++s)
+#pragma unroll
+        for (int w = 0; w < WMAX; ++w)
+            if (w == W - 1 && (row[s][w] & ~lm)) bad = true;
+#pragma unroll
+    for (int cw = 0; cw < WMAX; ++cw) {
+        if (cw >= W) break;
+        for (int cb = 0; cb < 64; ++cb) {
+            const int c = 64 * cw + cb;
+            if (c >= n) break;
+#pragma unroll
+            for (int s = 0; s < WMAX; ++s) {
+                if (s >= W) break;
+                const uint64_t col = __ballot((row[s][cw] >> cb) & 1ull);
+                if (col != sm.orig[c * W + s]) bad = true;
+            }
+        }
+    }
+    if (__ballot(bad)) {
+        if (lane == 0) {
+            *out.status = HLF_ENOTSYM;
+            *out.rank = 0;
+        }
+        return;
+    }
+
+    // Gauss-Jordan over GF(2), column by column.
+    int r = 0, nfree = 0;
+#pragma unroll
+    for (int cw = 0; cw < WMAX; ++cw) {
+        if (cw >= W) break;
+        for (int cb = 0; cb < 64; ++cb) {
+            const int c = 64 * cw + cb;
+            if (c >= n) break;
+            int ps = -1, pl = 0;
+#pragma unroll
+            for (int s = 0; s < WMAX; ++s) {
+                const bool cand = (s < W) && !used[s] && ((row[s][cw] >> cb) & 1ull);
+                const uint64_t m = __ballot(cand);
+                if (ps < 0 && m) {
+                    ps = s;
+                    pl = __builtin_ctzll(m);
+                }
+            }
+            if (ps < 0) {
+                if (lane == 0) sm.freec[nfree] = c;
+                ++nfree;
+                continue;
+            }
+            pl = __builtin_amdgcn_readfirstlane(pl);
+            uint64_t prow[WMAX];
+#pragma unroll
+            for (int w = 0; w < WMAX; ++w) prow[w] = 0;
+#pragma unroll
+            for (int s = 0; s < WMAX; ++s)
+                if (s == ps)
+#pragma unroll
+                    for (int w = 0; w < WMAX; ++w) prow[w] = readlane64(row[s][w], pl);
+#pragma unroll
+            for (int s = 0; s < WMAX; ++s) {
+                const bool is_p = (s == ps) && (lane == pl);
+                if (((row[s][cw] >> cb) & 1ull) && !is_p)
+#pragma unroll
+                    for (int w = 0; w < WMAX; ++w) row[s][w] ^= prow[w];
+                if (is_p) {
+                    used[s] = true;
+                    rk[s] = r;
+                }
+            }
+            if (lane == 0) sm.piv[r] = c;
+            ++r;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < WMAX; ++s)
+        if (used[s])
+#pragma unroll
+            for (int w = 0; w < WMAX; ++w)
+                if (w < W) sm.rref[rk[s] * W + w] = row[s][w];
+    __syncthreads();
+
+    for (int k = lane; k < n; k += 64) out.pivots[k] = (k < r) ? sm.piv[k] : -1;
+    for (int idx = lane; idx < r * W; idx += 64) {
+        const int k = idx / W, w = idx - k * W;
+        out.basis[idx] = sm.orig[sm.piv[k] * W + w];
+    }
+
+    // Kernel vectors k_f and q(k_f) = sum_{i in supp k_f} popcount(A_i & k_f).
+    const int nk = n - r;
+    for (int j = lane; j < nk; j += 64) {
+        const int f = sm.freec[j];
+        uint64_t kv[WMAX];
+#pragma unroll
+        for (int w = 0; w < WMAX; ++w) kv[w] = 0;
+        set_bit<WMAX>(kv, f);
+        for (int k = 0; k < r; ++k) {
+            if ((sm.rref[k * W + (f >> 6)] >> (f & 63)) & 1ull) set_bit<WMAX>(kv, sm.piv[k]);
+        }
+        if (out.kernel)
+#pragma unroll
+            for (int w = 0; w < WMAX; ++w)
+                if (w < W) out.kernel[j * W + w] = kv[w];
+        uint32_t q = 0;
+#pragma unroll
+        for (int iw = 0; iw < WMAX; ++iw) {
+            uint64_t bits = kv[iw];
+            while (bits) {
+                const int i = iw * 64 + __builtin_ctzll(bits);
+                bits &= bits - 1;
+#pragma unroll
+                for (int w = 0; w < WMAX; ++w)
+                    if (w < W) q += __builtin_popcountll(sm.orig[i * W + w] & kv[w]);
+            }
+        }
+        if (q & 1u) sm.internal = 1;
+        if (q & 2u) atomicOr(&sm.shiftw[f >> 6], 1ull << (f & 63));
+    }
+    __syncthreads();
+    if (lane < W) out.shift[lane] = sm.shiftw[lane];
+    if (lane == 0) {
+        *out.rank = r;
+        *out.status = sm.internal ? HLF_EINTERNAL : HLF_OK;
+    }
+}
+
+template <int WMAX>
+__global__ __launch_bounds__(64) void factor_wave_kernel(const uint64_t *__restrict__ rows, int n,
+                                                         int W, FactorOut out) {
+    __shared__ WaveSmem<WMAX> sm;
+    factor_wave<WMAX>(rows, n, W, out, sm);
+}
+
+// ---------------------------------------------------------------------------
+// A1-A4, workgroup variant: n <= 64*WMAX <= 1024, 64*W threads, thread i
+// holds row i.  The LDS matrix `mat` (n rows of W words) first holds A for
+// the symmetry check, then the RREF rows (0..r-1) and the kernel vectors
+// (r..n-1).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lower_bound_int(const int *a, int len, int key) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+template <int WMAX>
+__global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *__restrict__ rows,
+                                                                int n, int W, FactorOut out) {
+    __shared__ uint64_t mat[64 * WMAX * WMAX];
+    __shared__ uint64_t prow[WMAX];
+    __shared__ int piv[64 * WMAX];
+    __shared__ int freec[64 * WMAX];
+    __shared__ int qacc[64 * WMAX];
+    __shared__ int cand[3];
+    __shared__ unsigned long long shiftw[WMAX];
+    __shared__ int flag_bad, flag_internal;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int nthr = blockDim.x;
+
+    uint64_t row[WMAX];
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w) {
+        row[w] = (tid < n && w < W) ? rows[tid * W + w] : 0ull;
+        if (tid < n && w < W) mat[tid * W + w] = row[w];
+    }
+    if (tid < WMAX) shiftw[tid] = 0;
+    if (tid < 3) cand[tid] = INT_MAX;
+    if (tid == 0) {
+        flag_bad = 0;
+        flag_internal = 0;
+    }
+    __syncthreads();
+
+    bool bad = false;
+    const uint64_t lm = last_word_mask(n);
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w)
+        if (w == W - 1 && (row[w] & ~lm)) bad = true;
+#pragma unroll
+    for (int cw = 0; cw < WMAX; ++cw) {
+        if (cw >= W) break;
+        for (int cb = 0; cb < 64; ++cb) {
+            const int c = 64 * cw + cb;
+            if (c >= n) break;
+            const uint64_t col = __ballot((row[cw] >> cb) & 1ull);
+            if (col != mat[c * W + wave]) bad = true;
+        }
+    }
+    if (bad) flag_bad = 1;
+    __syncthreads();
+    if (flag_bad) {
+        if (tid == 0) {
+            *out.status = HLF_ENOTSYM;
+            *out.rank = 0;
+        }
+        return;
+    }
+
+    int r = 0, nfree = 0, slot = 0;
+    bool used = false;
+    int myk = -1;
+#pragma unroll
+    for (int cw = 0; cw < WMAX; ++cw) {
+        if (cw >= W) break;
+        for (int cb = 0; cb < 64; ++cb) {
+            const int c = 64 * cw + cb;
+            if (c >= n) break;
+            const bool hit = (row[cw] >> cb) & 1ull;
+            const uint64_t m = __ballot(tid < n && !used && hit);
+            if (lane == 0 && m) atomicMin(&cand[slot], wave * 64 + __builtin_ctzll(m));
+            __syncthreads();
+            const int p = cand[slot];
+            // The slot of column c+2 was last read during column c-1, which
+            // every thread finished before the barrier above.
+            if (tid == 0) cand[slot == 0 ? 2 : slot - 1] = INT_MAX;
+            slot = (slot == 2) ? 0 : slot + 1;
+            if (p == INT_MAX) {
+                if (tid == 0) freec[nfree] = c;
+                ++nfree;
+                continue;
+            }
+            if (tid == p) {
+#pragma unroll
+                for (int w = 0; w < WMAX; ++w) prow[w] = row[w];
+                used = true;
+                myk = r;
+            }
+            if (tid == 0) piv[r] = c;
+            __syncthreads();
+            if (hit && tid != p) {
+#pragma unroll
+                for (int w = 0; w < WMAX; ++w)
+                    if (w < W) row[w] ^= prow[w];
+            }
+            ++r;
+        }
+    }
+    __syncthreads();
+    if (used)
+#pragma unroll
+        for (int w = 0; w < WMAX; ++w)
+            if (w < W) mat[myk * W + w] = row[w];
+    const int nk = n - r;
+    if (tid < nk) qacc[tid] = 0;
+    __syncthreads();
+
+    // Kernel vectors: word w of k_f collects RREF[k][f] at the pivots of word w.
+    for (int idx = tid; idx < nk * W; idx += nthr) {
+        const int j = idx / W, w = idx - j * W;
+        const int f = freec[j];
+        uint64_t v = ((f >> 6) == w) ? (1ull << (f & 63)) : 0ull;
+        const int klo = lower_bound_int(piv, r, 64 * w);
+        const int khi = lower_bound_int(piv, r, 64 * w + 64);
+        for (int k = klo; k < khi; ++k)
+            if ((mat[k * W + (f >> 6)] >> (f & 63)) & 1ull) v |= 1ull << (piv[k] & 63);
+        mat[(r + j) * W + w] = v;
+        if (out.kernel) out.kernel[j * W + w] = v;
+    }
+    __syncthreads();
+
+    // q(k_f): thread i adds popcount(A_i & k_f) when bit i of k_f is set.
+    if (tid < n) {
+        uint64_t arow[WMAX];
+#pragma unroll
+        for (int w = 0; w < WMAX; ++w) arow[w] = (w < W) ? rows[tid * W + w] : 0ull;
+        for (int j = 0; j < nk; ++j) {
+            const uint64_t *kv = &mat[(r + j) * W];
+            if ((kv[tid >> 6] >> (tid & 63)) & 1ull) {
+                int cnt = 0;
+#pragma unroll
+                for (int w = 0; w < WMAX; ++w)
+                    if (w < W) cnt += __builtin_popcountll(arow[w] & kv[w]);
+                atomicAdd(&qacc[j], cnt);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < nk) {
+        const int q = qacc[tid];
+        const int f = freec[tid];
+        if (q & 1) flag_internal = 1;
+        if (q & 2) atomicOr(&shiftw[f >> 6], 1ull << (f & 63));
+    }
+    __syncthreads();
+
+    for (int k = tid; k < n; k += nthr) out.pivots[k] = (k < r) ? piv[k] : -1;
+    for (int idx = tid; idx < r * W; idx += nthr) {
+        const int k = idx / W, w = idx - k * W;
+        out.basis[idx] = rows[piv[k] * W + w];
+    }
+    if (tid < W) out.shift[tid] = shiftw[tid];
+    if (tid == 0) {
+        *out.rank = r;
+        *out.status = flag_internal ? HLF_EINTERNAL : HLF_OK;
+    }
+}
+
+template <int WMAX>
+hlf_status launch_pack_t(const uint8_t *A, int n, int W, uint64_t *rows, int32_t *status,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(pack_dense_kernel<WMAX>, dim3(1), dim3(64 * W), 0, stream, A, n, W, rows,
+                       status);
+    return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
+}
+
+template <int WMAX>
+hlf_status launch_wave_t(const uint64_t *rows, int n, int W, const FactorOut &out,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(factor_wave_kernel<WMAX>, dim3(1), dim3(64), 0, stream, rows, n, W, out);
+    return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
+}
+
+template <int WMAX>
+hlf_status launch_workgroup_t(const uint64_t *rows, int n, int W, const FactorOut &out,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL(factor_workgroup_kernel<WMAX>, dim3(1), dim3(64 * W), 0, stream, rows, n,
+                       W, out);
+    return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
+}
+
+}  // namespace
+
+hlf_status launch_pack(const uint8_t *A, int n, int W, uint64_t *rows, int32_t *status,
+                       hipStream_t stream) {
+    if (W <= 1) return launch_pack_t<1>(A, n, W, rows, status, stream);
+    if (W <= 2) return launch_pack_t<2>(A, n, W, rows, status, stream);
+    if (W <= 3) return launch_pack_t<3>(A, n, W, rows, status, stream);
+    if (W <= 4) return launch_pack_t<4>(A, n, W, rows, status, stream);
+    if (W <= 8) return launch_pack_t<8>(A, n, W, rows, status, stream);
+    return launch_pack_t<16>(A, n, W, rows, status, stream);
+}
+
+hlf_status launch_factor(const uint64_t *rows, int n, int W, const FactorOut &out,
+                         bool force_workgroup, hipStream_t stream) {
+    if (!force_workgroup) {
+        if (W == 1) return launch_wave_t<1>(rows, n, W, out, stream);
+        if (W == 2) return launch_wave_t<2>(rows, n, W, out, stream);
+        if (W == 3) return launch_wave_t<3>(rows, n, W, out, stream);
+    }
+    if (W <= 1) return launch_workgroup_t<1>(rows, n, W, out, stream);
+    if (W <= 2) return launch_workgroup_t<2>(rows, n, W, out, stream);
+    if (W <= 4) return launch_workgroup_t<4>(rows, n, W, out, stream);
+    if (W <= 8) return launch_workgroup_t<8>(rows, n, W, out, stream);
+    return launch_workgroup_t<16>(rows, n, W, out, stream);
+}
+
+}  // namespace hlf

@@ -1,0 +1,52 @@
+// Device-side helpers shared by the HIP kernels of libhlf (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hlf.h"
+
+namespace hlf {
+
+constexpr int kWave = 64;
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+// Output function of SplitMix64 (Stafford's Mix13), used for the set hash and
+// the sampling coefficient stream.
+__device__ __forceinline__ uint64_t mix13(uint64_t x) {
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_xor_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v ^= __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// Mask of the valid bits of the last word of an n-bit vector (all ones when
+// n is a multiple of 64).
+__device__ __forceinline__ uint64_t last_word_mask(int n) {
+    int rem = n & 63;
+    return rem ? ((1ull << rem) - 1) : ~0ull;
+}
+
+}  // namespace hlf

@@ -1,0 +1,45 @@
+// Host-side internal interface between the C ABI (hlf_abi.cpp) and the
+// kernel launchers (one per .hip file).
+#pragma once
+
+#include <stdint.h>
+
+#include "hlf.h"
+
+namespace hlf {
+
+// Output pointers of one factor record.
+struct FactorOut {
+    int32_t *status;
+    int32_t *rank;
+    int32_t *pivots;
+    uint64_t *basis;
+    uint64_t *shift;
+    uint64_t *kernel;  // may be null
+};
+
+// Read-only view of a factor record for the stage-2 kernels.
+struct FactorIn {
+    int32_t n;
+    int32_t words;
+    int32_t *status;        // read, and set to HLF_ERANGE on a bad range
+    const int32_t *rank;
+    const uint64_t *basis;
+    const uint64_t *shift;
+};
+
+int device_cu_count();
+
+hlf_status launch_pack(const uint8_t *A, int n, int W, uint64_t *rows, int32_t *status,
+                       hipStream_t stream);
+hlf_status launch_factor(const uint64_t *rows, int n, int W, const FactorOut &out,
+                         bool force_workgroup, hipStream_t stream);
+hlf_status launch_enumerate(const FactorIn &f, uint64_t begin, uint64_t count, int word_bits,
+                            void *out, hipStream_t stream);
+hlf_status launch_reduce(const FactorIn &f, uint64_t begin, uint64_t count, bool accumulate,
+                         uint64_t *counts, uint64_t *hash, uint64_t *xorfold,
+                         hipStream_t stream);
+hlf_status launch_sample(const FactorIn &f, uint64_t seed, uint64_t num, const uint64_t *coeffs,
+                         uint64_t *out, hipStream_t stream);
+
+}  // namespace hlf

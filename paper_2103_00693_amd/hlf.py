@@ -1,0 +1,245 @@
+"""Thin ctypes binding of libhlf.so (the C ABI declared in include/hlf.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libhlf.so.  PyTorch provides device memory and the current stream.
+uint64 data lives in int64 tensors (same bits); ``as_uint64`` reinterprets a
+host copy.  If libhlf.so is missing, every call raises ``HlfError``: there is
+no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhlf.so")
+
+HLF_OK = 0
+HLF_EINVAL = -1
+HLF_ENOTSYM = -2
+HLF_ERANGE = -3
+HLF_ENOMEM = -4
+HLF_EDEVICE = -5
+HLF_ECANCELLED = -6
+HLF_EINTERNAL = -7
+HLF_MAX_N = 1024
+HLF_MAX_ENUM_RANK = 62
+HLF_ACCUMULATE = 1
+HLF_FACTOR_WORKGROUP = 1
+
+EXPORTED = (
+    "hlf_version", "hlf_status_string", "hlf_words_for", "hlf_pack_dense", "hlf_factor",
+    "hlf_factor_ex", "hlf_enumerate", "hlf_enumerate_reduce", "hlf_sample",
+)
+
+
+class HlfError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        self.code = code
+        msg = status_string(code) if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg}" if where else msg)
+
+
+class _Factors(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("words", ctypes.c_int32),
+        ("status", ctypes.c_void_p),
+        ("rank", ctypes.c_void_p),
+        ("pivots", ctypes.c_void_p),
+        ("basis", ctypes.c_void_p),
+        ("shift", ctypes.c_void_p),
+        ("kernel", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhlf.so (raises HlfError if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HlfError(HLF_EDEVICE, f"{LIB_PATH} is missing; build it with "
+                                        "`python -m paper_2103_00693_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+        fp = ctypes.POINTER(_Factors)
+        L.hlf_version.restype = i32
+        L.hlf_status_string.restype = ctypes.c_char_p
+        L.hlf_status_string.argtypes = [i32]
+        L.hlf_words_for.restype = i32
+        L.hlf_words_for.argtypes = [i32]
+        L.hlf_pack_dense.restype = i32
+        L.hlf_pack_dense.argtypes = [vp, i32, vp, vp, vp]
+        L.hlf_factor.restype = i32
+        L.hlf_factor.argtypes = [vp, fp, vp]
+        L.hlf_factor_ex.restype = i32
+        L.hlf_factor_ex.argtypes = [vp, fp, u32, vp]
+        L.hlf_enumerate.restype = i32
+        L.hlf_enumerate.argtypes = [fp, u64, u64, i32, vp, vp]
+        L.hlf_enumerate_reduce.restype = i32
+        L.hlf_enumerate_reduce.argtypes = [fp, u64, u64, u32, vp, vp, vp, vp]
+        L.hlf_sample.restype = i32
+        L.hlf_sample.argtypes = [fp, u64, u64, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().hlf_status_string(int(code)).decode()
+
+
+def words_for(n: int) -> int:
+    return (n + 63) // 64
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check(code: int, where: str):
+    if code != HLF_OK:
+        raise HlfError(code, where)
+
+
+def as_uint64(t: torch.Tensor) -> np.ndarray:
+    """Host copy of an int64 tensor viewed as uint64."""
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+class Factors:
+    """A device-resident factor record (hlf_factors) whose buffers are tensors."""
+
+    def __init__(self, n: int, device=None, kernel: bool = True):
+        if not 1 <= n <= HLF_MAX_N:
+            raise HlfError(HLF_EINVAL, f"n={n} outside [1, {HLF_MAX_N}]")
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        W = words_for(n)
+        self.n, self.words, self.device = n, W, dev
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.rank = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.pivots = torch.full((n,), -1, dtype=torch.int32, device=dev)
+        self.basis = torch.zeros((n, W), dtype=torch.int64, device=dev)
+        self.shift = torch.zeros(W, dtype=torch.int64, device=dev)
+        self.kernel = torch.zeros((n, W), dtype=torch.int64, device=dev) if kernel else None
+        self._c = _Factors(n, W, self.status.data_ptr(), self.rank.data_ptr(),
+                           self.pivots.data_ptr(), self.basis.data_ptr(), self.shift.data_ptr(),
+                           self.kernel.data_ptr() if kernel else 0)
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+    def check(self):
+        """Synchronise and raise HlfError if the device status is not HLF_OK."""
+        code = int(self.status.item())
+        if code != HLF_OK:
+            raise HlfError(code, "device status")
+        return self
+
+    def read(self) -> dict:
+        """Synchronise and return the record as Python ints (bit j of an int is z_{j+1})."""
+        status = int(self.status.item())
+        r = int(self.rank.item())
+        W = self.words
+        basis = as_uint64(self.basis)
+        shift = as_uint64(self.shift)
+
+        def to_int(row):
+            return sum(int(row[w]) << (64 * w) for w in range(W))
+
+        out = {
+            "status": status,
+            "n": self.n,
+            "words": W,
+            "rank": r,
+            "pivots": [int(p) for p in self.pivots.cpu().tolist()],
+            "basis": [to_int(basis[k]) for k in range(r)],
+            "shift": to_int(shift),
+        }
+        if self.kernel is not None:
+            kern = as_uint64(self.kernel)
+            out["kernel"] = [to_int(kern[j]) for j in range(self.n - r)]
+        return out
+
+
+def pack_dense(A: torch.Tensor, rows: torch.Tensor | None = None,
+               status: torch.Tensor | None = None, stream=None):
+    """A0: hlf_pack_dense on a uint8 (n, n) device tensor -> (rows, status)."""
+    if A.dtype != torch.uint8 or A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise HlfError(HLF_EINVAL, "A must be a square uint8 tensor")
+    A = A.contiguous()
+    n = A.shape[0]
+    W = words_for(n)
+    if rows is None:
+        rows = torch.empty((n, W), dtype=torch.int64, device=A.device)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=A.device)
+    _check(lib().hlf_pack_dense(_ptr(A), n, _ptr(rows), _ptr(status), _stream(stream)),
+           "hlf_pack_dense")
+    return rows, status
+
+
+def factor(rows: torch.Tensor, n: int, F: Factors | None = None, workgroup: bool = False,
+           stream=None) -> Factors:
+    """A1-A4: hlf_factor(_ex) of packed rows into a device record."""
+    if F is None:
+        F = Factors(n, device=rows.device)
+    flags = HLF_FACTOR_WORKGROUP if workgroup else 0
+    _check(lib().hlf_factor_ex(_ptr(rows), F.c, flags, _stream(stream)), "hlf_factor")
+    return F
+
+
+_DTYPES = {16: torch.int16, 32: torch.int32, 64: torch.int64}
+
+
+def enumerate_solutions(F: Factors, begin: int, count: int, word_bits: int,
+                        out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """E1: hlf_enumerate into ``out`` (allocated when None)."""
+    if out is None:
+        if word_bits in _DTYPES and F.n <= word_bits:
+            out = torch.empty(count, dtype=_DTYPES[word_bits], device=F.device)
+        else:
+            out = torch.empty((count, word_bits // 64), dtype=torch.int64, device=F.device)
+    _check(lib().hlf_enumerate(F.c, begin, count, word_bits, _ptr(out) if count else None,
+                               _stream(stream)), "hlf_enumerate")
+    return out
+
+
+def enumerate_reduce(F: Factors, begin: int, count: int, accumulate: bool = False,
+                     counts: torch.Tensor | None = None, hash_out: torch.Tensor | None = None,
+                     xorfold: torch.Tensor | None = None, want_xorfold: bool = True,
+                     stream=None):
+    """E2: hlf_enumerate_reduce -> (counts int64[n], hash int64[1], xorfold int64[W] or None)."""
+    dev = F.device
+    if counts is None:
+        counts = torch.zeros(F.n, dtype=torch.int64, device=dev)
+    if hash_out is None:
+        hash_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    if xorfold is None and want_xorfold:
+        xorfold = torch.zeros(F.words, dtype=torch.int64, device=dev)
+    flags = HLF_ACCUMULATE if accumulate else 0
+    _check(lib().hlf_enumerate_reduce(F.c, begin, count, flags, _ptr(counts), _ptr(hash_out),
+                                      _ptr(xorfold), _stream(stream)), "hlf_enumerate_reduce")
+    return counts, hash_out, xorfold
+
+
+def sample(F: Factors, seed: int, num: int, coeffs: torch.Tensor | None = None,
+           out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """S1: hlf_sample -> int64 (num, W)."""
+    if out is None:
+        out = torch.empty((num, F.words), dtype=torch.int64, device=F.device)
+    _check(lib().hlf_sample(F.c, seed & ((1 << 64) - 1), num, _ptr(coeffs),
+                            _ptr(out) if num else None, _stream(stream)), "hlf_sample")
+    return out

@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/hlf.h, and rejects host-detectable bad
+arguments before touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2103_00693_amd import hlf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(hlf_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_header_declares_the_binding_names():
+    assert declared_symbols() == set(hlf.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = hlf.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_scalar_helpers():
+    L = hlf.lib()
+    assert L.hlf_version() >> 16 == 1
+    assert [L.hlf_words_for(n) for n in (1, 64, 65, 128, 129, 1024)] == [1, 1, 2, 2, 3, 16]
+    assert "ERANGE" in hlf.status_string(hlf.HLF_ERANGE)
+
+
+def _rec(n, null=None):
+    W = (n + 63) // 64
+    f = hlf._Factors(n, W, 8, 8, 8, 8, 8, 0)
+    if null:
+        setattr(f, null, 0)
+    return f
+
+
+@pytest.mark.parametrize("null", ["status", "rank", "pivots", "basis", "shift"])
+def test_factor_rejects_null_record_members(null):
+    L = hlf.lib()
+    f = _rec(10, null)
+    assert L.hlf_factor(ctypes.c_void_p(8), ctypes.byref(f), None) == hlf.HLF_EINVAL
+
+
+def test_host_detected_errors():
+    L = hlf.lib()
+    good = _rec(10)
+    assert L.hlf_factor(None, ctypes.byref(good), None) == hlf.HLF_EINVAL
+    bad_n = _rec(10)
+    bad_n.n = 0
+    assert L.hlf_factor(ctypes.c_void_p(8), ctypes.byref(bad_n), None) == hlf.HLF_EINVAL
+    big = _rec(10)
+    big.n, big.words = 1025, 17
+    assert L.hlf_factor(ctypes.c_void_p(8), ctypes.byref(big), None) == hlf.HLF_EINVAL
+    wrong_w = _rec(100)
+    wrong_w.words = 1
+    assert L.hlf_factor(ctypes.c_void_p(8), ctypes.byref(wrong_w), None) == hlf.HLF_EINVAL
+    assert L.hlf_factor_ex(ctypes.c_void_p(8), ctypes.byref(good), 2, None) == hlf.HLF_EINVAL
+    assert L.hlf_pack_dense(None, 4, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == hlf.HLF_EINVAL
+    assert L.hlf_pack_dense(ctypes.c_void_p(8), 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == hlf.HLF_EINVAL
+    assert L.hlf_pack_dense(ctypes.c_void_p(8), 1025, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == hlf.HLF_EINVAL
+    # word_bits must hold n, or be 64*W
+    f20 = _rec(20)
+    assert L.hlf_enumerate(ctypes.byref(f20), 0, 4, 8, ctypes.c_void_p(16), None) == hlf.HLF_EINVAL
+    assert L.hlf_enumerate(ctypes.byref(f20), 0, 4, 16, ctypes.c_void_p(16), None) == hlf.HLF_EINVAL
+    assert L.hlf_enumerate(ctypes.byref(f20), 0, 4, 128, ctypes.c_void_p(16), None) == hlf.HLF_EINVAL
+    f100 = _rec(100)
+    assert L.hlf_enumerate(ctypes.byref(f100), 0, 4, 64, ctypes.c_void_p(16), None) == hlf.HLF_EINVAL
+    assert L.hlf_enumerate(ctypes.byref(f20), 0, 4, 32, None, None) == hlf.HLF_EINVAL
+    # count == 0 is a no-op that succeeds without touching the device
+    assert L.hlf_enumerate(ctypes.byref(f20), 0, 0, 32, None, None) == hlf.HLF_OK
+    assert L.hlf_sample(ctypes.byref(f20), 1, 0, None, None, None) == hlf.HLF_OK
+    assert L.hlf_sample(ctypes.byref(f20), 1, 5, None, None, None) == hlf.HLF_EINVAL
+    assert L.hlf_enumerate_reduce(ctypes.byref(f20), 0, 4, 0, None, ctypes.c_void_p(8), None, None) == hlf.HLF_EINVAL
+    assert L.hlf_enumerate_reduce(ctypes.byref(f20), 0, 4, 4, ctypes.c_void_p(8), ctypes.c_void_p(8), None, None) == hlf.HLF_EINVAL
+
+
+def test_product_package_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2103_00693_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, fn)).read()
+                assert "oracle" not in src.lower(), fn

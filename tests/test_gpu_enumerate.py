@@ -1,0 +1,188 @@
+"""GPU parity of the materialise path (hlf_enumerate) against the oracle.
+
+Full arrays are compared element by element at the benchmark's full sizes
+(all 2^r solutions of every N=5 seed) and at small sizes that span several
+tiles with ragged heads and tails; edge cases cover r = 0, 1, 2, unaligned
+begin and output pointers, 64-bit and multiword outputs, and status handling.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from hlf_inputs import CONFIG2_SEEDS, grid_instance, random_symmetric
+from oracle import c_oracle as C
+from oracle import hlf_oracle as O
+from paper_2103_00693_amd import hlf
+
+from gpu_util import gpu_factor, narrow_to_u64, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _embedded(n, m, seed):
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(n, size=m, replace=False))
+    A = np.zeros((n, n), dtype=np.uint8)
+    A[np.ix_(idx, idx)] = random_symmetric(m, seed, density=0.3)
+    return A
+
+
+def gpu_enum(F, begin, count, word_bits):
+    out = hlf.enumerate_solutions(F, begin, count, word_bits)
+    torch.cuda.synchronize()
+    assert int(F.status.item()) == hlf.HLF_OK
+    return out
+
+
+def ref_enum(Fo, begin, count):
+    return C.enumerate_range(Fo, begin, count)
+
+
+def test_config1_full_all_formats():
+    A = grid_instance(4, seed=0)
+    Fo = O.factor(A)
+    r = Fo["rank"]
+    print(f"[enum] config1 r={r}", flush=True)
+    F, _ = gpu_factor(A)
+    ref = ref_enum(Fo, 0, 1 << r)[:, 0]
+    for wb in (16, 32, 64):
+        got = narrow_to_u64(gpu_enum(F, 0, 1 << r, wb))
+        assert np.array_equal(got, ref), wb
+
+
+@pytest.mark.parametrize("seed", CONFIG2_SEEDS)
+def test_config2_full_u32(seed):
+    A = grid_instance(5, seed=seed)
+    Fo = O.factor(A)
+    r = Fo["rank"]
+    print(f"[enum] config2 seed={seed} r={r} count={1 << r}", flush=True)
+    F, _ = gpu_factor(A)
+    got = narrow_to_u64(gpu_enum(F, 0, 1 << r, 32))
+    ref = ref_enum(Fo, 0, 1 << r)[:, 0]
+    assert np.array_equal(got, ref)
+    # successive solutions differ by B_ctz(i) (Gray step), checked on the GPU output itself
+    idx = np.arange(1, 1 << 16, dtype=np.uint64)
+    ctz = np.array([(int(i) & -int(i)).bit_length() - 1 for i in idx])
+    B = np.array(Fo["basis"], dtype=np.uint64)
+    assert np.array_equal(got[1:1 << 16] ^ got[:(1 << 16) - 1], B[ctz])
+    # all distinct
+    assert np.unique(got).size == got.size
+
+
+RANGES = [(1, 1000), (3, 4095), (5, 1), (1023, 1025), (4, 4096 * 3 + 7), (12345678, (1 << 20) + 7),
+          (8, 1 << 21)]
+
+
+@pytest.mark.parametrize("word_bits", [32, 64])
+def test_ragged_and_unaligned_ranges(word_bits):
+    A = grid_instance(5, seed=2)  # r = 25
+    Fo = O.factor(A)
+    r = Fo["rank"]
+    F, _ = gpu_factor(A)
+    for begin, count in RANGES + [((1 << r) - 3, 3), ((1 << r) - 1000, 1000)]:
+        print(f"[enum] ragged wb={word_bits} begin={begin} count={count}", flush=True)
+        got = narrow_to_u64(gpu_enum(F, begin, count, word_bits))
+        assert np.array_equal(got, ref_enum(Fo, begin, count)[:, 0]), (begin, count)
+
+
+def test_misaligned_output_pointer():
+    A = grid_instance(5, seed=4)
+    Fo = O.factor(A)
+    F, _ = gpu_factor(A)
+    for wb, dt in ((32, torch.int32), (64, torch.int64)):
+        big = torch.zeros(70001, dtype=dt, device="cuda")
+        view = big[1:]  # 4- or 8-byte offset from a 256-byte aligned base
+        print(f"[enum] misaligned out wb={wb}", flush=True)
+        hlf.enumerate_solutions(F, 64, 70000, wb, out=view)
+        torch.cuda.synchronize()
+        got = narrow_to_u64(view)
+        assert np.array_equal(got, ref_enum(Fo, 64, 70000)[:, 0])
+        assert int(big[0].item()) == 0
+
+
+@pytest.mark.parametrize("name,A", [
+    ("zero n=5 (r=0)", np.zeros((5, 5), dtype=np.uint8)),
+    ("1x1 one (r=1)", np.ones((1, 1), dtype=np.uint8)),
+    ("2x2 b=0000 (r=2)", grid_instance(2, b="0000")),
+    ("2x2 b=1011 (r=3)", grid_instance(2, b="1011")),
+    ("3x3 p=0.3", grid_instance(3, p=0.3, seed=8)),
+    ("n=64 embedded", _embedded(64, 30, 4)),
+])
+def test_small_rank_edge_cases(name, A):
+    Fo = O.factor(A)
+    r = Fo["rank"]
+    n = A.shape[0]
+    F, _ = gpu_factor(A)
+    ref = ref_enum(Fo, 0, 1 << r)[:, 0]
+    for wb in (16, 32, 64):
+        if n > wb:
+            continue
+        print(f"[enum] {name} r={r} wb={wb}", flush=True)
+        got = narrow_to_u64(gpu_enum(F, 0, 1 << r, wb))
+        assert np.array_equal(got, ref)
+        if r >= 1:
+            got2 = narrow_to_u64(gpu_enum(F, 1, (1 << r) - 1, wb))
+            assert np.array_equal(got2, ref[1:])
+
+
+@pytest.mark.parametrize("n,m,seed", [(65, 40, 1), (100, 50, 2), (200, 33, 3), (1024, 40, 4)])
+def test_multiword(n, m, seed):
+    A = _embedded(n, m, seed)
+    Fo = O.factor(A)
+    r = Fo["rank"]
+    W = (n + 63) // 64
+    F, _ = gpu_factor(A)
+    for begin, count in [(0, min(1 << r, 5000)), (3, min((1 << r) - 3, 777)), ((1 << r) - 300, 300)]:
+        print(f"[enum] multiword n={n} r={r} begin={begin} count={count}", flush=True)
+        got = gpu_enum(F, begin, count, 64 * W)
+        ref = ref_enum(Fo, begin, count)
+        assert np.array_equal(hlf.as_uint64(got).reshape(count, W), ref)
+
+
+def test_out_of_range_sets_erange_and_writes_nothing():
+    A = grid_instance(4, seed=0)
+    Fo = O.factor(A)
+    r = Fo["rank"]
+    F, _ = gpu_factor(A)
+    out = torch.full((100,), -7, dtype=torch.int32, device="cuda")
+    print("[enum] erange", flush=True)
+    hlf.enumerate_solutions(F, (1 << r) - 50, 100, 32, out=out)
+    torch.cuda.synchronize()
+    assert int(F.status.item()) == hlf.HLF_ERANGE
+    assert bool((out == -7).all())
+    # the record stays poisoned: later calls write nothing
+    hlf.enumerate_solutions(F, 0, 10, 32, out=out)
+    torch.cuda.synchronize()
+    assert bool((out == -7).all())
+
+
+def test_rank_above_62_is_erange():
+    A = random_symmetric(100, 1, 0.5)
+    Fo = O.factor(A)
+    assert Fo["rank"] > 62
+    F, _ = gpu_factor(A)
+    out = torch.full((8, 2), -1, dtype=torch.int64, device="cuda")
+    print("[enum] r>62", flush=True)
+    hlf.enumerate_solutions(F, 0, 8, 128, out=out)
+    torch.cuda.synchronize()
+    assert int(F.status.item()) == hlf.HLF_ERANGE
+    assert bool((out == -1).all())
+
+
+def test_invalid_matrix_propagates_status():
+    A = grid_instance(4, seed=1)
+    A[0, 5] = 1  # not symmetric
+    F, st = gpu_factor(A)
+    assert st == hlf.HLF_ENOTSYM
+    assert int(F.status.item()) == hlf.HLF_ENOTSYM
+    out = torch.full((16,), -3, dtype=torch.int32, device="cuda")
+    hlf.enumerate_solutions(F, 0, 16, 32, out=out)
+    torch.cuda.synchronize()
+    assert bool((out == -3).all())
+    assert int(F.status.item()) == hlf.HLF_ENOTSYM
