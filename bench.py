@@ -31,8 +31,10 @@ HBM_PEAK_GBS = 8000.0
 # lanes x 2.4 GHz.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # VALU instructions per solution in the full-tile loop of the reduce kernel
-# (read from its gfx950 assembly): 2 XOR for z, 17 for mix13, 1 add.
-REDUCE_VALU_OPS_PER_SOLUTION = 20
+# (read from its gfx950 assembly): 2 XOR to form the input of the mix13 tail
+# (its GF(2)-linear first step is applied per lane and per tile), 14 for the
+# rest of mix13 (2 x [3 multiplies + add3], 2 x [64-bit shift + 2 XOR]), 1 add.
+REDUCE_VALU_OPS_PER_SOLUTION = 17
 METRIC = "solutions enumerated/s (G/s) + % HBM/VALU roofline; batched instances/s, p99 latency"
 
 
@@ -44,11 +46,96 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-modes", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (for HBM counter scaling)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 256 MiB, three times: the reference
+    kernel whose FETCH_SIZE / WRITE_SIZE counters scale the ones of the
+    enumerate kernel."""
+    import torch
+
+    src = torch.ones(1 << 25, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copied {src.numel() * 8} bytes x3", flush=True)
+
+
+def batch_mode(hlf, torch, stream, dev):
+    """4096 instances (N ~ U{3..12}, p ~ U{0.3, 0.5, 1.0}): factor every
+    instance and reduce every instance with r <= 28.  Batched: the tuned
+    persistent kernel replayed from a HIP graph.  Plain: one pack + factor
+    launch per instance, then one reduce per small-rank instance."""
+    from hlf_inputs import batch_instances
+
+    max_rank = 28
+    insts = batch_instances(4096, master_seed=0)
+    mats = [a for (_, _, _, a) in insts]
+    B = hlf.Batch([m.shape[0] for m in mats])
+    A = B.dense_input(mats, device=dev)
+    params, tune_ms = B.tune(A, max_rank, stream=stream)
+    B.graph_capture(A, max_rank, params)
+    B.graph_launch(stream=stream)
+    stream.synchronize()
+    reps = 5
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        B.graph_launch(stream=stream)
+    e1.record(stream)
+    stream.synchronize()
+    batched_s = e0.elapsed_time(e1) * 1e-3 / reps
+    ranks = [int(r) for r in B.ranks()]
+    counts_b, hashes_b = B.reduce_results()
+    sols = sum(1 << r for r in ranks if r <= max_rank)
+
+    # plain per-instance launches, same outputs
+    t0 = time.perf_counter()
+    Fs = []
+    with torch.cuda.stream(stream):
+        for m in mats:
+            n = m.shape[0]
+            Ad = torch.from_numpy(m).to(dev, non_blocking=False)
+            rows, _ = hlf.pack_dense(Ad, stream=stream)
+            Fs.append(hlf.factor(rows, n, hlf.Factors(n, device=dev, kernel=False), stream=stream))
+        stream.synchronize()
+        rp = [int(F.rank.item()) for F in Fs]
+        outs = {}
+        for i, F in enumerate(Fs):
+            if rp[i] <= max_rank:
+                outs[i] = hlf.enumerate_reduce(F, 0, 1 << rp[i], want_xorfold=False, stream=stream)
+        stream.synchronize()
+    plain_s = time.perf_counter() - t0
+    same = rp == ranks and all(
+        int(hlf.as_uint64(h)[0]) == hashes_b[i] and
+        (hlf.as_uint64(c) == counts_b[i]).all() for i, (c, h, _) in outs.items())
+    B.close()
+    return {
+        "workload": "4096 grid instances, N ~ U{3..12}, p ~ U{0.3,0.5,1.0}, diagonal Bernoulli(0.5): "
+                    "factor all, reduce (counts + hash) every instance with r <= 28",
+        "reduced_instances": len(outs),
+        "solutions": sols,
+        "batched": {"instances_per_s": round(4096 / batched_s, 1), "ms": round(batched_s * 1e3, 3),
+                    "solutions_per_s_G": round(sols / batched_s / 1e9, 2),
+                    "params": {"chunk_log2": params.chunk_log2, "waves_per_cu": params.waves_per_cu},
+                    "launch": "hipGraph replay of queue reset + one persistent kernel"},
+        "plain": {"instances_per_s": round(4096 / plain_s, 1), "ms": round(plain_s * 1e3, 3),
+                  "launch": "pack + factor per instance, then reduce per small-rank instance (host timed)"},
+        "speedup": round(plain_s / batched_s, 2),
+        "identical_outputs": bool(same),
+    }
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
                                    "the multi-GPU sharding is described in DESIGN.md"}))
@@ -66,41 +153,36 @@ def main():
 
     # ---------------- headline workload: N=5 grid, 8 seeds ----------------
     n = 25
-    insts = []
-    with torch.cuda.stream(stream):
-        for s in CONFIG2_SEEDS:
-            A = torch.from_numpy(grid_instance(5, seed=s)).to(dev)
-            rows = torch.empty((n, 1), dtype=torch.int64, device=dev)
-            st = torch.empty(1, dtype=torch.int32, device=dev)
-            F = hlf.Factors(n, device=dev, kernel=True)
-            hlf.pack_dense(A, rows, st, stream=stream)
-            hlf.factor(rows, n, F, stream=stream)
-            insts.append({"seed": s, "A": A, "rows": rows, "st": st, "F": F})
+    mats = [grid_instance(5, seed=s) for s in CONFIG2_SEEDS]
+    B = hlf.Batch([n] * len(mats))
+    A = B.dense_input(mats, device=dev)
+    B.factor_dense(A, stream=stream)
     stream.synchronize()
-    for it in insts:
-        it["F"].check()
-        it["r"] = int(it["F"].rank.item())
-        it["count"] = 1 << it["r"]
-        it["out"] = torch.empty(it["count"], dtype=torch.int32, device=dev)
-    solutions_per_step = sum(it["count"] for it in insts)
+    if not all(st == hlf.HLF_OK for st in B.statuses()):
+        raise RuntimeError("factor failed")
+    ranks = [int(r) for r in B.ranks()]
+    counts = [1 << r for r in ranks]
+    outs = [torch.empty(c, dtype=torch.int32, device=dev) for c in counts]
+    inst = list(range(len(mats)))
+    zeros = [0] * len(mats)
+    solutions_per_step = sum(counts)
     bytes_per_step = 4 * solutions_per_step
 
     def step(events=None):
-        for k, it in enumerate(insts):
-            hlf.pack_dense(it["A"], it["rows"], it["st"], stream=stream)
-            hlf.factor(it["rows"], n, it["F"], stream=stream)
-            if events is not None:
-                events[k][0].record(stream)
-            hlf.enumerate_solutions(it["F"], 0, it["count"], 32, out=it["out"], stream=stream)
-            if events is not None:
-                events[k][1].record(stream)
+        # stage 1 for all 8 instances (one launch), then stage 2 for all 8 (one launch)
+        B.factor_dense(A, stream=stream)
+        if events is not None:
+            events[0].record(stream)
+        B.enumerate(inst, zeros, counts, outs, 32, stream=stream)
+        if events is not None:
+            events[1].record(stream)
 
     for _ in range(args.warmup):
         step()
     stream.synchronize()
 
-    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
-           for _ in insts] for _ in range(args.steps)]
+    ev = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+          for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -108,15 +190,14 @@ def main():
     stream.synchronize()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for it in insts:
-        it["F"].check()
+    if not all(st == hlf.HLF_OK for st in B.statuses()):
+        raise RuntimeError("enumerate failed")
 
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = solutions_per_step * args.steps / elapsed / 1e9
-    enum_ms = [ev[k][j][0].elapsed_time(ev[k][j][1]) for k in range(args.steps) for j in range(len(insts))]
-    enum_bytes = [4 * it["count"] for _ in range(args.steps) for it in insts]
-    achieved_gbs = sum(enum_bytes) / (sum(enum_ms) * 1e-3) / 1e9
+    enum_ms = [e[0].elapsed_time(e[1]) for e in ev]
+    achieved_gbs = bytes_per_step * len(enum_ms) / (sum(enum_ms) * 1e-3) / 1e9
 
     result = {
         "metric": METRIC,
@@ -134,21 +215,21 @@ def main():
         "config": {
             "workload": "N=5 grid (n=25), all edges, diagonal Bernoulli(0.5), seeds 0-7: "
                         "pack + factor + materialise all 2^r solutions as uint32 per seed",
-            "instances": len(insts),
-            "ranks": [it["r"] for it in insts],
+            "instances": len(mats),
+            "ranks": ranks,
             "solutions_per_step": solutions_per_step,
             "bytes_written_per_step": bytes_per_step,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "enum_tile_kernel<uint32_t>",
+            "kernel": "batch_enum_kernel<uint32_t> (all 8 instances in one launch)",
             "achieved": round(achieved_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
             "traffic": None,
             "avg_launch_us": round(1e3 * sum(enum_ms) / len(enum_ms), 3),
-            "algorithmic_bytes_per_launch": sum(enum_bytes) // len(enum_bytes),
+            "algorithmic_bytes_per_launch": bytes_per_step,
         },
         "context": {"fpga_solutions_per_s": 1.0e8,
                     "fpga": "Kintex-7 XC7K410T at 100 MHz, one solution per clock (paper, Section 4)"},
@@ -193,7 +274,7 @@ def main():
             "ranks": ranks,
             "value": round(rate / 1e9, 2),
             "unit": "G solutions/s",
-            "roofline": {"bound": "alu", "kernel": "reduce_tile_kernel<8>",
+            "roofline": {"bound": "alu", "kernel": "reduce_wave_kernel<1>",
                          "achieved": round(ops, 2), "peak": round(VALU_PEAK_TOPS, 2),
                          "unit": "T VALU instr-lane-ops/s", "frac": round(ops / VALU_PEAK_TOPS, 4),
                          "valu_ops_per_solution": REDUCE_VALU_OPS_PER_SOLUTION},
@@ -223,6 +304,7 @@ def main():
                            "rank": int(F.rank.item()), "samples_per_s": round(65536 / smp_s, 1),
                            "ms_per_65536": round(smp_s * 1e3, 4),
                            "factor_ms_n1024": round(fac_s * 1e3, 4)}
+        modes["batch"] = batch_mode(hlf, torch, stream, dev)
         result["modes"] = modes
 
     # ---------------- CPU baseline: the oracle, on this host ----------------

@@ -48,7 +48,8 @@
  *
  * Memory and streams.  Every pointer named *_dev is caller-owned device memory
  *   on the current HIP device; the library does not allocate, free or keep any
- *   of it.  Every call is asynchronous on the caller's stream and returns once
+ *   of it.  The single-instance entry points never allocate; a batch (below)
+ *   allocates its own result arrays once, in hlf_batch_create.  Every call is asynchronous on the caller's stream and returns once
  *   the work is enqueued.  Calls on different streams are independent; calls
  *   that write the same buffers must be ordered by the caller.
  *
@@ -176,6 +177,100 @@ hlf_status hlf_enumerate_reduce(const hlf_factors *f, uint64_t begin, uint64_t c
  * Works for any r (no 62-bit limit).  num = 0 enqueues nothing.                 */
 hlf_status hlf_sample(const hlf_factors *f, uint64_t seed, uint64_t num,
                       const uint64_t *coeffs_dev, uint64_t *out_dev, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many instances of mixed n handled by one launch per stage (the
+ * FS2D workload over a set of grid instances, Sections 1-2 applied per
+ * instance).  A batch owns its device result arrays; they are allocated once
+ * by hlf_batch_create (not on the hot path) and freed by hlf_batch_destroy.
+ *
+ * Input layout: the dense matrices of all instances concatenated, instance i
+ * as a row-major n_i x n_i uint8 block at byte offset dense_off[i] = sum of
+ * n_k^2 over k < i.  Result layout (offsets reported by hlf_batch_get_layout):
+ * instance i's record fields sit at mat_off[i] (basis, kernel: n_i*W_i
+ * words), vec_off[i] (shift: W_i words) and piv_off[i] (pivots, counts: n_i
+ * entries); status, rank and hash are indexed by i.
+ * ------------------------------------------------------------------------- */
+typedef struct hlf_batch_s *hlf_batch;
+
+typedef struct hlf_batch_layout {
+    int32_t count;             /* number of instances I                          */
+    int32_t max_n;             /* largest n_i                                    */
+    int64_t dense_bytes;       /* sum n_i^2: bytes of the concatenated input     */
+    int64_t mat_words;         /* sum n_i * W_i                                  */
+    int64_t vec_words;         /* sum W_i                                        */
+    int64_t piv_entries;       /* sum n_i                                        */
+    const int64_t *dense_off;  /* host [I], owned by the batch                   */
+    const int64_t *mat_off;    /* host [I]                                       */
+    const int64_t *vec_off;    /* host [I]                                       */
+    const int64_t *piv_off;    /* host [I]                                       */
+    int32_t *status;           /* dev [I]                                        */
+    int32_t *rank;             /* dev [I]                                        */
+    int32_t *pivots;           /* dev [piv_entries]                              */
+    uint64_t *basis;           /* dev [mat_words]                                */
+    uint64_t *shift;           /* dev [vec_words]                                */
+    uint64_t *kernel;          /* dev [mat_words]                                */
+    uint64_t *counts;          /* dev [piv_entries]: reduce counts               */
+    uint64_t *hash;            /* dev [I]: reduce hash                           */
+} hlf_batch_layout;
+
+/* Launch parameters of hlf_batch_reduce: chunks of 2^chunk_log2 solutions
+ * (10..30) are the unit of dynamic scheduling; waves_per_cu (1..16) sizes the
+ * persistent grid.  hlf_batch_tune picks both by timing the real batch.       */
+typedef struct hlf_batch_params {
+    int32_t chunk_log2;
+    int32_t waves_per_cu;
+} hlf_batch_params;
+
+/* Create a batch of `count` (1..2^20) instances with n_host[i] vertices
+ * (1..HLF_MAX_N) on the current device.  Allocates the device arrays.
+ * Returns HLF_EINVAL for bad arguments, HLF_ENOMEM if allocation fails.       */
+hlf_status hlf_batch_create(int32_t count, const int32_t *n_host, hlf_batch *out);
+
+/* Free a batch (waits for the device).  NULL is accepted.                     */
+hlf_status hlf_batch_destroy(hlf_batch b);
+
+/* Offsets and device pointers of a batch.                                     */
+hlf_status hlf_batch_get_layout(hlf_batch b, hlf_batch_layout *layout);
+
+/* Stage 1 for every instance (pack + validate + factor, Section 1 and
+ * Section 2 tasks (1)-(4)): one launch for all instances with n_i <= 192 (a
+ * wavefront each), one workgroup launch per larger instance.  A_dev is the
+ * concatenated dense input.  Writes every record field of every instance.     */
+hlf_status hlf_batch_factor_dense(hlf_batch b, const uint8_t *A_dev, hipStream_t stream);
+
+/* Stage 2 materialise for `num` instances at once: out[k][i - begin[k]] = z_i
+ * of instance inst[k] for i in [begin[k], begin[k] + count[k]).  inst, begin,
+ * count and out are host arrays of length num; out[k] are device buffers.
+ * word_bits 16/32/64 with n_i <= word_bits for every listed instance.  Device
+ * errors go to the instance's status as in hlf_enumerate.                    */
+hlf_status hlf_batch_enumerate(hlf_batch b, int32_t num, const int32_t *inst,
+                               const uint64_t *begin, const uint64_t *count, void *const *out,
+                               int32_t word_bits, hipStream_t stream);
+
+/* Stage 1 + stage 2 reduce for the whole batch in ONE persistent launch (plus
+ * one small launch that resets its work queue): wavefronts first take factor
+ * tasks; every instance with rank <= max_rank (<= 62) then publishes its
+ * 2^r solutions as chunks on a device queue, which all wavefronts drain.
+ * Results: counts[piv_off[i] + j], hash[i] over all 2^r_i solutions (zero
+ * for instances with r_i > max_rank).  Needs max_n <= 192 (else HLF_EINVAL).
+ * params NULL selects defaults (or the tuned values, if hlf_batch_tune ran). */
+hlf_status hlf_batch_reduce(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,
+                            const hlf_batch_params *params, hipStream_t stream);
+
+/* Autotuner: times hlf_batch_reduce on this batch over a grid of
+ * (chunk_log2, waves_per_cu) candidates on `stream` (synchronising it) and
+ * stores the fastest as the batch default; *best and *best_ms receive it.
+ * Every candidate produces the same results.                                  */
+hlf_status hlf_batch_tune(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,
+                          hlf_batch_params *best, float *best_ms, hipStream_t stream);
+
+/* Capture hlf_batch_reduce(b, A_dev, max_rank, params) into a HIP graph owned
+ * by the batch (replacing a previous one) and replay it with
+ * hlf_batch_graph_launch.  A_dev must stay valid while the graph is used.    */
+hlf_status hlf_batch_graph_capture(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,
+                                   const hlf_batch_params *params);
+hlf_status hlf_batch_graph_launch(hlf_batch b, hipStream_t stream);
 
 #ifdef __cplusplus
 }

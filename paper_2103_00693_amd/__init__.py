@@ -6,6 +6,8 @@ The computation runs in the HIP kernels of ``libhlf.so`` (C ABI:
 
 from .hlf import (  # noqa: F401
     EXPORTED,
+    Batch,
+    BatchParams,
     Factors,
     HlfError,
     as_uint64,

@@ -10,6 +10,7 @@
 //     ballots, the pivot row broadcast through LDS.
 // Both variants produce the canonical record defined in hlf.h (the RREF is
 // unique, so the pivot rows chosen do not matter).
+#include "factor_wave.h"
 #include "hlf_device.h"
 #include "hlf_internal.h"
 
@@ -70,183 +71,12 @@ __global__ __launch_bounds__(64 * WMAX) void pack_dense_kernel(const uint8_t *__
     if (tid == 0) *status = bad ? HLF_ENOTSYM : HLF_OK;
 }
 
-// ---------------------------------------------------------------------------
-// A1-A4, wavefront variant: n <= 64*WMAX, WMAX in {1,2,3}.  Lane l holds rows
-// l, l+64, l+128 ("slots").  Launched with one 64-thread workgroup per
-// instance, so __syncthreads is a single-wave barrier.
-// ---------------------------------------------------------------------------
-template <int WMAX>
-struct WaveSmem {
-    uint64_t orig[64 * WMAX * WMAX];  // A, packed
-    uint64_t rref[64 * WMAX * WMAX];  // RREF row k at k*W
-    int piv[64 * WMAX];
-    int freec[64 * WMAX];
-    unsigned long long shiftw[WMAX];
-    int internal;
-};
-
-template <int WMAX>
-__device__ __forceinline__ void set_bit(uint64_t (&v)[WMAX], int pos) {
-#pragma unroll
-    for (int w = 0; w < WMAX; ++w)
-        if (w == (pos >> 6)) v[w] |= 1ull << (pos & 63);
-}
-
-template <int WMAX>
-__device__ void factor_wave(const uint64_t *__restrict__ rows, int n, int W, const FactorOut &out,
-                            WaveSmem<WMAX> &sm) {
-    const int lane = lane_id();
-    for (int idx = lane; idx < n * W; idx += 64) sm.orig[idx] = rows[idx];
-    if (lane < WMAX) sm.shiftw[lane] = 0;
-    if (lane == 0) sm.internal = 0;
-    __syncthreads();
-
-    uint64_t row[WMAX][WMAX];
-    bool used[WMAX];
-    int rk[WMAX];
-#pragma unroll
-    for (int s = 0; s < WMAX; ++s) {
-        const int i = s * 64 + lane;
-#pragma unroll
-        for (int w = 0; w < WMAX; ++w) row[s][w] = (i < n && w < W) ? sm.orig[i * W + w] : 0ull;
-        used[s] = false;
-        rk[s] = -1;
-    }
-
-    // Validation: pad bits zero, A = A^T (ballot over slot s = word s of a column).
-    bool bad = false;
-    const uint64_t lm = last_word_mask(n);
-#pragma unroll
-    for (int s = 0; s < WMAX; ++s)
-#pragma unroll
-        for (int w = 0; w < WMAX; ++w)
-            if (w == W - 1 && (row[s][w] & ~lm)) bad = true;
-#pragma unroll
-    for (int cw = 0; cw < WMAX; ++cw) {
-        if (cw >= W) break;
-        for (int cb = 0; cb < 64; ++cb) {
-            const int c = 64 * cw + cb;
-            if (c >= n) break;
-#pragma unroll
-            for (int s = 0; s < WMAX; ++s) {
-                if (s >= W) break;
-                const uint64_t col = __ballot((row[s][cw] >> cb) & 1ull);
-                if (col != sm.orig[c * W + s]) bad = true;
-            }
-        }
-    }
-    if (__ballot(bad)) {
-        if (lane == 0) {
-            *out.status = HLF_ENOTSYM;
-            *out.rank = 0;
-        }
-        return;
-    }
-
-    // Gauss-Jordan over GF(2), column by column.
-    int r = 0, nfree = 0;
-#pragma unroll
-    for (int cw = 0; cw < WMAX; ++cw) {
-        if (cw >= W) break;
-        for (int cb = 0; cb < 64; ++cb) {
-            const int c = 64 * cw + cb;
-            if (c >= n) break;
-            int ps = -1, pl = 0;
-#pragma unroll
-            for (int s = 0; s < WMAX; ++s) {
-                const bool cand = (s < W) && !used[s] && ((row[s][cw] >> cb) & 1ull);
-                const uint64_t m = __ballot(cand);
-                if (ps < 0 && m) {
-                    ps = s;
-                    pl = __builtin_ctzll(m);
-                }
-            }
-            if (ps < 0) {
-                if (lane == 0) sm.freec[nfree] = c;
-                ++nfree;
-                continue;
-            }
-            pl = __builtin_amdgcn_readfirstlane(pl);
-            uint64_t prow[WMAX];
-#pragma unroll
-            for (int w = 0; w < WMAX; ++w) prow[w] = 0;
-#pragma unroll
-            for (int s = 0; s < WMAX; ++s)
-                if (s == ps)
-#pragma unroll
-                    for (int w = 0; w < WMAX; ++w) prow[w] = readlane64(row[s][w], pl);
-#pragma unroll
-            for (int s = 0; s < WMAX; ++s) {
-                const bool is_p = (s == ps) && (lane == pl);
-                if (((row[s][cw] >> cb) & 1ull) && !is_p)
-#pragma unroll
-                    for (int w = 0; w < WMAX; ++w) row[s][w] ^= prow[w];
-                if (is_p) {
-                    used[s] = true;
-                    rk[s] = r;
-                }
-            }
-            if (lane == 0) sm.piv[r] = c;
-            ++r;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < WMAX; ++s)
-        if (used[s])
-#pragma unroll
-            for (int w = 0; w < WMAX; ++w)
-                if (w < W) sm.rref[rk[s] * W + w] = row[s][w];
-    __syncthreads();
-
-    for (int k = lane; k < n; k += 64) out.pivots[k] = (k < r) ? sm.piv[k] : -1;
-    for (int idx = lane; idx < r * W; idx += 64) {
-        const int k = idx / W, w = idx - k * W;
-        out.basis[idx] = sm.orig[sm.piv[k] * W + w];
-    }
-
-    // Kernel vectors k_f and q(k_f) = sum_{i in supp k_f} popcount(A_i & k_f).
-    const int nk = n - r;
-    for (int j = lane; j < nk; j += 64) {
-        const int f = sm.freec[j];
-        uint64_t kv[WMAX];
-#pragma unroll
-        for (int w = 0; w < WMAX; ++w) kv[w] = 0;
-        set_bit<WMAX>(kv, f);
-        for (int k = 0; k < r; ++k) {
-            if ((sm.rref[k * W + (f >> 6)] >> (f & 63)) & 1ull) set_bit<WMAX>(kv, sm.piv[k]);
-        }
-        if (out.kernel)
-#pragma unroll
-            for (int w = 0; w < WMAX; ++w)
-                if (w < W) out.kernel[j * W + w] = kv[w];
-        uint32_t q = 0;
-#pragma unroll
-        for (int iw = 0; iw < WMAX; ++iw) {
-            uint64_t bits = kv[iw];
-            while (bits) {
-                const int i = iw * 64 + __builtin_ctzll(bits);
-                bits &= bits - 1;
-#pragma unroll
-                for (int w = 0; w < WMAX; ++w)
-                    if (w < W) q += __builtin_popcountll(sm.orig[i * W + w] & kv[w]);
-            }
-        }
-        if (q & 1u) sm.internal = 1;
-        if (q & 2u) atomicOr(&sm.shiftw[f >> 6], 1ull << (f & 63));
-    }
-    __syncthreads();
-    if (lane < W) out.shift[lane] = sm.shiftw[lane];
-    if (lane == 0) {
-        *out.rank = r;
-        *out.status = sm.internal ? HLF_EINTERNAL : HLF_OK;
-    }
-}
-
 template <int WMAX>
 __global__ __launch_bounds__(64) void factor_wave_kernel(const uint64_t *__restrict__ rows, int n,
                                                          int W, FactorOut out) {
     __shared__ WaveSmem<WMAX> sm;
-    factor_wave<WMAX>(rows, n, W, out, sm);
+    wave_load_rows<WMAX>(rows, n, W, sm);
+    factor_wave_core<WMAX>(n, W, false, out, sm);
 }
 
 // ---------------------------------------------------------------------------

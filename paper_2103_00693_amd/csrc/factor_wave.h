@@ -1,0 +1,218 @@
+// Stage 1 (the paper's CLA module, Section 2, tasks (1)-(4)) for one
+// instance with n <= 64*WMAX (WMAX in {1,2,3}) on one wavefront.
+//
+// Lane l holds rows l, l+64, l+128 ("slots") in VGPRs.  Gauss-Jordan over
+// GF(2) takes a ballot per slot to find the candidate rows of a column, picks
+// the lowest, broadcasts it with readlane and XORs it into every other row
+// that has the column set -- no barriers, no LDS in the elimination.  The
+// reduced rows then give the Ker(A) basis (task (2)), q on it (task (3)) and
+// the canonical shift (task (4)).
+//
+// Callers launch 64-thread workgroups (one wave), so __syncthreads below is a
+// single-wave barrier and an early return of the wave is safe.
+#pragma once
+
+#include "hlf_device.h"
+#include "hlf_internal.h"
+
+namespace hlf {
+
+template <int WMAX>
+struct WaveSmem {
+    uint64_t orig[64 * WMAX * WMAX];  // A, packed rows of W words
+    uint64_t rref[64 * WMAX * WMAX];  // RREF row k at k*W
+    int piv[64 * WMAX];
+    int freec[64 * WMAX];
+    unsigned long long shiftw[WMAX];
+    int internal;
+};
+
+template <int WMAX>
+__device__ __forceinline__ void set_bit(uint64_t (&v)[WMAX], int pos) {
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w)
+        if (w == (pos >> 6)) v[w] |= 1ull << (pos & 63);
+}
+
+// Packed rows from global memory into sm.orig.
+template <int WMAX>
+__device__ __forceinline__ void wave_load_rows(const uint64_t *__restrict__ rows, int n, int W,
+                                               WaveSmem<WMAX> &sm) {
+    for (int idx = lane_id(); idx < n * W; idx += 64) sm.orig[idx] = rows[idx];
+}
+
+// Dense row-major uint8 matrix into sm.orig (pack by ballot over 64
+// consecutive bytes).  Returns true on every lane if an entry is not 0/1.
+template <int WMAX>
+__device__ __forceinline__ bool wave_load_dense(const uint8_t *__restrict__ A, int n, int W,
+                                                WaveSmem<WMAX> &sm) {
+    const int lane = lane_id();
+    bool bad = false;
+    for (int i = 0; i < n; ++i) {
+        const uint8_t *src = A + (size_t)i * n;
+        for (int w = 0; w < W; ++w) {
+            const int j = 64 * w + lane;
+            const uint8_t v = (j < n) ? src[j] : (uint8_t)0;
+            bad |= (v > 1);
+            const uint64_t word = __ballot(v == 1);
+            if (lane == 0) sm.orig[i * W + w] = word;
+        }
+    }
+    return __ballot(bad) != 0;
+}
+
+// Factor the matrix in sm.orig.  `bad_input` forces HLF_ENOTSYM.  Returns the
+// rank, or -1 if the record was marked invalid.
+template <int WMAX>
+__device__ int factor_wave_core(int n, int W, bool bad_input, const FactorOut &out,
+                                WaveSmem<WMAX> &sm) {
+    const int lane = lane_id();
+    if (lane < WMAX) sm.shiftw[lane] = 0;
+    if (lane == 0) sm.internal = 0;
+    __syncthreads();
+
+    uint64_t row[WMAX][WMAX];
+    bool used[WMAX];
+    int rk[WMAX];
+#pragma unroll
+    for (int s = 0; s < WMAX; ++s) {
+        const int i = s * 64 + lane;
+#pragma unroll
+        for (int w = 0; w < WMAX; ++w) row[s][w] = (i < n && w < W) ? sm.orig[i * W + w] : 0ull;
+        used[s] = false;
+        rk[s] = -1;
+    }
+
+    // Validation: pad bits zero, A = A^T (the ballot of bit c over slot s is
+    // word s of column c, which must equal word s of row c).
+    bool bad = bad_input;
+    const uint64_t lm = last_word_mask(n);
+#pragma unroll
+    for (int s = 0; s < WMAX; ++s)
+#pragma unroll
+        for (int w = 0; w < WMAX; ++w)
+            if (w == W - 1 && (row[s][w] & ~lm)) bad = true;
+#pragma unroll
+    for (int cw = 0; cw < WMAX; ++cw) {
+        if (cw >= W) break;
+        for (int cb = 0; cb < 64; ++cb) {
+            const int c = 64 * cw + cb;
+            if (c >= n) break;
+#pragma unroll
+            for (int s = 0; s < WMAX; ++s) {
+                if (s >= W) break;
+                const uint64_t col = __ballot((row[s][cw] >> cb) & 1ull);
+                if (col != sm.orig[c * W + s]) bad = true;
+            }
+        }
+    }
+    if (__ballot(bad)) {
+        if (lane == 0) {
+            *out.rank = 0;
+            *out.status = HLF_ENOTSYM;
+        }
+        return -1;
+    }
+
+    // Gauss-Jordan over GF(2), column by column.
+    int r = 0, nfree = 0;
+#pragma unroll
+    for (int cw = 0; cw < WMAX; ++cw) {
+        if (cw >= W) break;
+        for (int cb = 0; cb < 64; ++cb) {
+            const int c = 64 * cw + cb;
+            if (c >= n) break;
+            int ps = -1, pl = 0;
+#pragma unroll
+            for (int s = 0; s < WMAX; ++s) {
+                const bool cand = (s < W) && !used[s] && ((row[s][cw] >> cb) & 1ull);
+                const uint64_t m = __ballot(cand);
+                if (ps < 0 && m) {
+                    ps = s;
+                    pl = __builtin_ctzll(m);
+                }
+            }
+            if (ps < 0) {
+                if (lane == 0) sm.freec[nfree] = c;
+                ++nfree;
+                continue;
+            }
+            pl = __builtin_amdgcn_readfirstlane(pl);
+            uint64_t prow[WMAX];
+#pragma unroll
+            for (int w = 0; w < WMAX; ++w) prow[w] = 0;
+#pragma unroll
+            for (int s = 0; s < WMAX; ++s)
+                if (s == ps)
+#pragma unroll
+                    for (int w = 0; w < WMAX; ++w) prow[w] = readlane64(row[s][w], pl);
+#pragma unroll
+            for (int s = 0; s < WMAX; ++s) {
+                const bool is_p = (s == ps) && (lane == pl);
+                if (((row[s][cw] >> cb) & 1ull) && !is_p)
+#pragma unroll
+                    for (int w = 0; w < WMAX; ++w) row[s][w] ^= prow[w];
+                if (is_p) {
+                    used[s] = true;
+                    rk[s] = r;
+                }
+            }
+            if (lane == 0) sm.piv[r] = c;
+            ++r;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < WMAX; ++s)
+        if (used[s])
+#pragma unroll
+            for (int w = 0; w < WMAX; ++w)
+                if (w < W) sm.rref[rk[s] * W + w] = row[s][w];
+    __syncthreads();
+
+    for (int k = lane; k < n; k += 64) out.pivots[k] = (k < r) ? sm.piv[k] : -1;
+    for (int idx = lane; idx < r * W; idx += 64) {
+        const int k = idx / W, w = idx - k * W;
+        out.basis[idx] = sm.orig[sm.piv[k] * W + w];
+    }
+
+    // Kernel vectors k_f and q(k_f) = sum_{i in supp k_f} popcount(A_i & k_f).
+    const int nk = n - r;
+    for (int j = lane; j < nk; j += 64) {
+        const int f = sm.freec[j];
+        uint64_t kv[WMAX];
+#pragma unroll
+        for (int w = 0; w < WMAX; ++w) kv[w] = 0;
+        set_bit<WMAX>(kv, f);
+        for (int k = 0; k < r; ++k) {
+            if ((sm.rref[k * W + (f >> 6)] >> (f & 63)) & 1ull) set_bit<WMAX>(kv, sm.piv[k]);
+        }
+        if (out.kernel)
+#pragma unroll
+            for (int w = 0; w < WMAX; ++w)
+                if (w < W) out.kernel[j * W + w] = kv[w];
+        uint32_t q = 0;
+#pragma unroll
+        for (int iw = 0; iw < WMAX; ++iw) {
+            uint64_t bits = kv[iw];
+            while (bits) {
+                const int i = iw * 64 + __builtin_ctzll(bits);
+                bits &= bits - 1;
+#pragma unroll
+                for (int w = 0; w < WMAX; ++w)
+                    if (w < W) q += __builtin_popcountll(sm.orig[i * W + w] & kv[w]);
+            }
+        }
+        if (q & 1u) sm.internal = 1;
+        if (q & 2u) atomicOr(&sm.shiftw[f >> 6], 1ull << (f & 63));
+    }
+    __syncthreads();
+    if (lane < W) out.shift[lane] = sm.shiftw[lane];
+    const bool internal = sm.internal != 0;
+    if (lane == 0) {
+        *out.rank = r;
+        *out.status = internal ? HLF_EINTERNAL : HLF_OK;
+    }
+    return internal ? -1 : r;
+}
+
+}  // namespace hlf

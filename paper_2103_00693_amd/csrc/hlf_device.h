@@ -22,9 +22,29 @@ __device__ __forceinline__ uint64_t mix13(uint64_t x) {
     return x;
 }
 
+// mix13 without its first step x ^= x >> 30.  That step is linear over GF(2),
+// so for x = a ^ b it equals (a ^ (a >> 30)) ^ (b ^ (b >> 30)); callers that
+// split x into a per-lane and a per-tile part pre-apply it to each part.
+__device__ __forceinline__ uint64_t mix13_tail(uint64_t x) {
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t mix13_head(uint64_t x) { return x ^ (x >> 30); }
+
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
     uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
     uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// A value that is the same on every lane, moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
 }
 

@@ -34,6 +34,9 @@ HLF_FACTOR_WORKGROUP = 1
 EXPORTED = (
     "hlf_version", "hlf_status_string", "hlf_words_for", "hlf_pack_dense", "hlf_factor",
     "hlf_factor_ex", "hlf_enumerate", "hlf_enumerate_reduce", "hlf_sample",
+    "hlf_batch_create", "hlf_batch_destroy", "hlf_batch_get_layout", "hlf_batch_factor_dense",
+    "hlf_batch_enumerate", "hlf_batch_reduce", "hlf_batch_tune", "hlf_batch_graph_capture",
+    "hlf_batch_graph_launch",
 )
 
 
@@ -243,3 +246,215 @@ def sample(F: Factors, seed: int, num: int, coeffs: torch.Tensor | None = None,
     _check(lib().hlf_sample(F.c, seed & ((1 << 64) - 1), num, _ptr(coeffs),
                             _ptr(out) if num else None, _stream(stream)), "hlf_sample")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Batches
+# ---------------------------------------------------------------------------
+
+class _BatchLayout(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int32),
+        ("max_n", ctypes.c_int32),
+        ("dense_bytes", ctypes.c_int64),
+        ("mat_words", ctypes.c_int64),
+        ("vec_words", ctypes.c_int64),
+        ("piv_entries", ctypes.c_int64),
+        ("dense_off", ctypes.POINTER(ctypes.c_int64)),
+        ("mat_off", ctypes.POINTER(ctypes.c_int64)),
+        ("vec_off", ctypes.POINTER(ctypes.c_int64)),
+        ("piv_off", ctypes.POINTER(ctypes.c_int64)),
+        ("status", ctypes.c_void_p),
+        ("rank", ctypes.c_void_p),
+        ("pivots", ctypes.c_void_p),
+        ("basis", ctypes.c_void_p),
+        ("shift", ctypes.c_void_p),
+        ("kernel", ctypes.c_void_p),
+        ("counts", ctypes.c_void_p),
+        ("hash", ctypes.c_void_p),
+    ]
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [("chunk_log2", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
+
+    def __repr__(self):
+        return f"BatchParams(chunk_log2={self.chunk_log2}, waves_per_cu={self.waves_per_cu})"
+
+
+_batch_sigs_done = False
+_hip = None
+
+
+def _batch_lib():
+    global _batch_sigs_done
+    L = lib()
+    if not _batch_sigs_done:
+        vp, i32, u64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)
+        L.hlf_batch_create.restype = i32
+        L.hlf_batch_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(vp)]
+        L.hlf_batch_destroy.restype = i32
+        L.hlf_batch_destroy.argtypes = [vp]
+        L.hlf_batch_get_layout.restype = i32
+        L.hlf_batch_get_layout.argtypes = [vp, ctypes.POINTER(_BatchLayout)]
+        L.hlf_batch_factor_dense.restype = i32
+        L.hlf_batch_factor_dense.argtypes = [vp, vp, vp]
+        L.hlf_batch_enumerate.restype = i32
+        L.hlf_batch_enumerate.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), u64p, u64p,
+                                          ctypes.POINTER(vp), i32, vp]
+        L.hlf_batch_reduce.restype = i32
+        L.hlf_batch_reduce.argtypes = [vp, vp, i32, ctypes.POINTER(BatchParams), vp]
+        L.hlf_batch_tune.restype = i32
+        L.hlf_batch_tune.argtypes = [vp, vp, i32, ctypes.POINTER(BatchParams),
+                                     ctypes.POINTER(ctypes.c_float), vp]
+        L.hlf_batch_graph_capture.restype = i32
+        L.hlf_batch_graph_capture.argtypes = [vp, vp, i32, ctypes.POINTER(BatchParams)]
+        L.hlf_batch_graph_launch.restype = i32
+        L.hlf_batch_graph_launch.argtypes = [vp, vp]
+        _batch_sigs_done = True
+    return L
+
+
+def _device_to_host(ptr: int, nbytes: int, dtype) -> np.ndarray:
+    """Copy nbytes from a device pointer owned by the library (after a sync)."""
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.restype = ctypes.c_int
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    out = np.empty(nbytes // np.dtype(dtype).itemsize, dtype=dtype)
+    if nbytes:
+        rc = _hip.hipMemcpy(out.ctypes.data, ctypes.c_void_p(ptr), nbytes, 2)  # device to host
+        if rc != 0:
+            raise HlfError(HLF_EDEVICE, f"hipMemcpy failed ({rc})")
+    return out
+
+
+class Batch:
+    """hlf_batch: many instances, one launch per stage (device arrays owned by the library)."""
+
+    def __init__(self, ns):
+        L = _batch_lib()
+        ns = [int(x) for x in ns]
+        arr = (ctypes.c_int32 * len(ns))(*ns)
+        h = ctypes.c_void_p()
+        _check(L.hlf_batch_create(len(ns), arr, ctypes.byref(h)), "hlf_batch_create")
+        self._h = h
+        self.ns = ns
+        lay = _BatchLayout()
+        _check(L.hlf_batch_get_layout(h, ctypes.byref(lay)), "hlf_batch_get_layout")
+        I = lay.count
+        self.count = I
+        self.max_n = lay.max_n
+        self.dense_bytes = lay.dense_bytes
+        self.mat_words, self.vec_words, self.piv_entries = lay.mat_words, lay.vec_words, lay.piv_entries
+        self.dense_off = np.ctypeslib.as_array(lay.dense_off, shape=(I,)).copy()
+        self.mat_off = np.ctypeslib.as_array(lay.mat_off, shape=(I,)).copy()
+        self.vec_off = np.ctypeslib.as_array(lay.vec_off, shape=(I,)).copy()
+        self.piv_off = np.ctypeslib.as_array(lay.piv_off, shape=(I,)).copy()
+        self.ptr = {k: getattr(lay, k) for k in ("status", "rank", "pivots", "basis", "shift",
+                                                  "kernel", "counts", "hash")}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _batch_lib().hlf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dense_input(self, mats, device=None) -> torch.Tensor:
+        """Concatenate dense uint8 matrices in the batch's input layout, on the device."""
+        host = np.zeros(self.dense_bytes, dtype=np.uint8)
+        for i, A in enumerate(mats):
+            n = self.ns[i]
+            a = np.ascontiguousarray(A, dtype=np.uint8)
+            if a.shape != (n, n):
+                raise HlfError(HLF_EINVAL, f"instance {i} must be {n}x{n}")
+            host[self.dense_off[i]:self.dense_off[i] + n * n] = a.reshape(-1)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        return torch.from_numpy(host).to(dev)
+
+    def factor_dense(self, A_dev: torch.Tensor, stream=None):
+        _check(_batch_lib().hlf_batch_factor_dense(self._h, _ptr(A_dev), _stream(stream)),
+               "hlf_batch_factor_dense")
+
+    def enumerate(self, inst, begin, count, outs, word_bits: int, stream=None):
+        num = len(inst)
+        ia = (ctypes.c_int32 * num)(*[int(x) for x in inst])
+        ba = (ctypes.c_uint64 * num)(*[int(x) for x in begin])
+        ca = (ctypes.c_uint64 * num)(*[int(x) for x in count])
+        oa = (ctypes.c_void_p * num)(*[o.data_ptr() for o in outs])
+        _check(_batch_lib().hlf_batch_enumerate(self._h, num, ia, ba, ca, oa, word_bits,
+                                                _stream(stream)), "hlf_batch_enumerate")
+
+    def reduce(self, A_dev: torch.Tensor, max_rank: int, params: BatchParams | None = None,
+               stream=None):
+        p = ctypes.byref(params) if params is not None else None
+        _check(_batch_lib().hlf_batch_reduce(self._h, _ptr(A_dev), max_rank, p, _stream(stream)),
+               "hlf_batch_reduce")
+
+    def tune(self, A_dev: torch.Tensor, max_rank: int, stream=None):
+        best = BatchParams()
+        ms = ctypes.c_float()
+        _check(_batch_lib().hlf_batch_tune(self._h, _ptr(A_dev), max_rank, ctypes.byref(best),
+                                           ctypes.byref(ms), _stream(stream)), "hlf_batch_tune")
+        return best, float(ms.value)
+
+    def graph_capture(self, A_dev: torch.Tensor, max_rank: int, params: BatchParams | None = None):
+        p = ctypes.byref(params) if params is not None else None
+        _check(_batch_lib().hlf_batch_graph_capture(self._h, _ptr(A_dev), max_rank, p),
+               "hlf_batch_graph_capture")
+
+    def graph_launch(self, stream=None):
+        _check(_batch_lib().hlf_batch_graph_launch(self._h, _stream(stream)), "hlf_batch_graph_launch")
+
+    # -- reading results (synchronise first) --
+    def _read(self, key, nbytes, dtype):
+        return _device_to_host(self.ptr[key], nbytes, dtype)
+
+    def statuses(self) -> np.ndarray:
+        torch.cuda.synchronize()
+        return self._read("status", 4 * self.count, np.int32)
+
+    def ranks(self) -> np.ndarray:
+        torch.cuda.synchronize()
+        return self._read("rank", 4 * self.count, np.int32)
+
+    def records(self) -> list[dict]:
+        """Every instance's record as Python ints (same layout as Factors.read)."""
+        torch.cuda.synchronize()
+        status = self._read("status", 4 * self.count, np.int32)
+        rank = self._read("rank", 4 * self.count, np.int32)
+        piv = self._read("pivots", 4 * self.piv_entries, np.int32)
+        basis = self._read("basis", 8 * self.mat_words, np.uint64)
+        shift = self._read("shift", 8 * self.vec_words, np.uint64)
+        kern = self._read("kernel", 8 * self.mat_words, np.uint64)
+        out = []
+        for i, n in enumerate(self.ns):
+            W = words_for(n)
+            r = int(rank[i])
+            mo, vo, po = int(self.mat_off[i]), int(self.vec_off[i]), int(self.piv_off[i])
+
+            def vec(arr, off):
+                return sum(int(arr[off + w]) << (64 * w) for w in range(W))
+
+            rec = {"status": int(status[i]), "n": n, "words": W, "rank": r,
+                   "pivots": [int(p) for p in piv[po:po + n]]}
+            if rec["status"] == HLF_OK:
+                rec["basis"] = [vec(basis, mo + k * W) for k in range(r)]
+                rec["shift"] = vec(shift, vo)
+                rec["kernel"] = [vec(kern, mo + j * W) for j in range(n - r)]
+            out.append(rec)
+        return out
+
+    def reduce_results(self):
+        """(counts per instance as uint64 arrays, hashes as Python ints)."""
+        torch.cuda.synchronize()
+        counts = self._read("counts", 8 * self.piv_entries, np.uint64)
+        hashes = self._read("hash", 8 * self.count, np.uint64)
+        return ([counts[int(self.piv_off[i]):int(self.piv_off[i]) + n] for i, n in enumerate(self.ns)],
+                [int(h) for h in hashes])

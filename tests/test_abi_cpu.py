@@ -95,3 +95,16 @@ def test_product_package_does_not_import_the_oracle():
             if fn.endswith((".py", ".hip", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, fn)).read()
                 assert "oracle" not in src.lower(), fn
+
+
+def test_batch_host_validation():
+    L = hlf._batch_lib()
+    h = ctypes.c_void_p()
+    ns = (ctypes.c_int32 * 3)(4, 0, 9)
+    assert L.hlf_batch_create(3, ns, ctypes.byref(h)) == hlf.HLF_EINVAL
+    ns2 = (ctypes.c_int32 * 1)(1025)
+    assert L.hlf_batch_create(1, ns2, ctypes.byref(h)) == hlf.HLF_EINVAL
+    assert L.hlf_batch_create(0, ns2, ctypes.byref(h)) == hlf.HLF_EINVAL
+    assert L.hlf_batch_destroy(None) == hlf.HLF_OK
+    assert L.hlf_batch_reduce(None, ctypes.c_void_p(8), 10, None, None) == hlf.HLF_EINVAL
+    assert L.hlf_batch_graph_launch(None, None) == hlf.HLF_EINVAL
