@@ -131,6 +131,46 @@ def batch_mode(hlf, torch, stream, dev):
     }
 
 
+def serve_mode(torch):
+    """Poisson arrivals of requests with N ~ U{4..32} (n = 16..1024), p = 0.5:
+    stage 1 + 65536 uniform samples, or the full enumeration when r <= 24.
+    Saturated throughput first (every request present at t = 0), then
+    arrival rates of 0.5, 0.8 and 0.95 of it; latency = arrival -> result in
+    host memory."""
+    from hlf_inputs import serve_requests
+    from paper_2103_00693_amd.serve import Request, Server, percentile
+
+    count = 200
+
+    def reqs(rate, seed):
+        return [Request(rid=k, A=q["A"], seed=q["seed"], arrival=q["t"])
+                for k, q in enumerate(serve_requests(count, rate, master_seed=seed))]
+
+    Server(slots=8).run(reqs(1000.0, 99)[:16], realtime=False)  # warm-up
+    srv = Server(slots=8)
+    t0 = time.perf_counter()
+    res = srv.run(reqs(1000.0, 1), realtime=False)
+    sat = count / (time.perf_counter() - t0)
+    out = {"workload": "requests with N ~ U{4..32} (n = 16..1024), p = 0.5, diagonal Bernoulli(0.5): "
+                       "stage 1 + 65536 uniform samples, or all 2^r solutions when r <= 24",
+           "slots": 8, "requests_per_run": count,
+           "saturated_requests_per_s": round(sat, 1),
+           "kinds": {k: sum(1 for r in res if r.kind == k) for k in ("sample", "enumerate", "error")},
+           "loads": []}
+    for frac in (0.5, 0.8, 0.95):
+        srv = Server(slots=8)
+        t0 = time.perf_counter()
+        res = srv.run(reqs(frac * sat, 2), realtime=True)
+        wall = time.perf_counter() - t0
+        lat = [r.latency * 1e3 for r in res]
+        out["loads"].append({"offered_fraction": frac, "offered_per_s": round(frac * sat, 1),
+                             "served_per_s": round(count / wall, 1),
+                             "p50_ms": round(percentile(lat, 50), 3),
+                             "p99_ms": round(percentile(lat, 99), 3),
+                             "max_in_flight_bytes": srv.max_in_flight})
+    return out
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -305,6 +345,7 @@ def main():
                            "ms_per_65536": round(smp_s * 1e3, 4),
                            "factor_ms_n1024": round(fac_s * 1e3, 4)}
         modes["batch"] = batch_mode(hlf, torch, stream, dev)
+        modes["serve"] = serve_mode(torch)
         result["modes"] = modes
 
     # ---------------- CPU baseline: the oracle, on this host ----------------

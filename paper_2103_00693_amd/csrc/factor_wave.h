@@ -41,21 +41,31 @@ __device__ __forceinline__ void wave_load_rows(const uint64_t *__restrict__ rows
     for (int idx = lane_id(); idx < n * W; idx += 64) sm.orig[idx] = rows[idx];
 }
 
-// Dense row-major uint8 matrix into sm.orig (pack by ballot over 64
-// consecutive bytes).  Returns true on every lane if an entry is not 0/1.
+// Dense row-major uint8 matrix into sm.orig: lane l reads column 64*w + l of
+// 32 rows at once (independent loads, one memory latency per group), and the
+// ballot over the 64 lanes of each row gives its packed word.  Returns true
+// on every lane if an entry is not 0/1.
 template <int WMAX>
 __device__ __forceinline__ bool wave_load_dense(const uint8_t *__restrict__ A, int n, int W,
                                                 WaveSmem<WMAX> &sm) {
+    constexpr int G = 32;
     const int lane = lane_id();
     bool bad = false;
-    for (int i = 0; i < n; ++i) {
-        const uint8_t *src = A + (size_t)i * n;
-        for (int w = 0; w < W; ++w) {
-            const int j = 64 * w + lane;
-            const uint8_t v = (j < n) ? src[j] : (uint8_t)0;
-            bad |= (v > 1);
-            const uint64_t word = __ballot(v == 1);
-            if (lane == 0) sm.orig[i * W + w] = word;
+    for (int w = 0; w < W; ++w) {
+        const int j = 64 * w + lane;
+        const bool jin = j < n;
+        for (int i0 = 0; i0 < n; i0 += G) {
+            uint32_t v[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+                v[k] = (jin && i0 + k < n) ? (uint32_t)A[(size_t)(i0 + k) * n + j] : 0u;
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                if (i0 + k >= n) break;
+                bad |= v[k] > 1u;
+                const uint64_t word = __ballot(v[k] == 1u);
+                if (lane == 0) sm.orig[(i0 + k) * W + w] = word;
+            }
         }
     }
     return __ballot(bad) != 0;
