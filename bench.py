@@ -35,6 +35,17 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (its GF(2)-linear first step is applied per lane and per tile), 14 for the
 # rest of mix13 (2 x [3 multiplies + add3], 2 x [64-bit shift + 2 XOR]), 1 add.
 REDUCE_VALU_OPS_PER_SOLUTION = 17
+# HBM traffic of one batch_enum_kernel<uint32_t> launch of the headline step,
+# from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), each scaled by what the same counter reads for a plain 256 MiB
+# device copy (WRITE_SIZE 262144 KiB -> x1.0, FETCH_SIZE 131085 KiB -> x2.0).
+# Valid only for the kernel sources it was taken on (sha256 prefix below).
+ENUM_TRAFFIC = {
+    "src_sha256_16": "f71dd4f21246543f",
+    "fetch_kib_raw": 53.4, "fetch_scale": 2.0,
+    "write_kib_raw": 688809.0, "write_scale": 1.0,
+}
+ENUM_TRAFFIC_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/batch.hip")
 METRIC = "solutions enumerated/s (G/s) + % HBM/VALU roofline; batched instances/s, p99 latency"
 
 
@@ -49,6 +60,21 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (for HBM counter scaling)")
     return ap.parse_args()
+
+
+def enum_traffic_bytes():
+    """Measured HBM bytes per launch of the headline kernel, or None if its
+    sources changed since the counters were taken."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in ENUM_TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != ENUM_TRAFFIC["src_sha256_16"]:
+        return None
+    t = ENUM_TRAFFIC
+    return int(1024 * (t["fetch_kib_raw"] * t["fetch_scale"] + t["write_kib_raw"] * t["write_scale"]))
 
 
 def copy_calibration():
@@ -267,7 +293,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": enum_traffic_bytes(),
             "avg_launch_us": round(1e3 * sum(enum_ms) / len(enum_ms), 3),
             "algorithmic_bytes_per_launch": bytes_per_step,
         },
