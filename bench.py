@@ -3,7 +3,8 @@
 Headline (the timed region): the N=5 grid workload -- n = 25 qubits, every
 nearest-neighbour edge, diagonal Bernoulli(0.5), seeds 0..7.  One step runs,
 for each of the 8 instances, pack -> factor -> materialise all 2^r solutions as
-uint32 words in HBM (2^23 .. 2^25 per instance).  Inputs are resident in HBM
+uint32 words in HBM (2^23 .. 2^25 per instance), all in one launch
+(hlf_batch_solve).  Inputs are resident in HBM
 before timing starts; outputs are preallocated.  `value` is solutions written
 per second over the whole step.
 
@@ -35,7 +36,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (its GF(2)-linear first step is applied per lane and per tile), 14 for the
 # rest of mix13 (2 x [3 multiplies + add3], 2 x [64-bit shift + 2 XOR]), 1 add.
 REDUCE_VALU_OPS_PER_SOLUTION = 17
-# HBM traffic of one batch_enum_kernel<uint32_t> launch of the headline step,
+# HBM traffic of one materialise launch of the headline step,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch), each scaled by what the same counter reads for a plain 256 MiB
 # device copy (WRITE_SIZE 262144 KiB -> x1.0, FETCH_SIZE 131085 KiB -> x2.0).
@@ -235,11 +236,10 @@ def main():
     bytes_per_step = 4 * solutions_per_step
 
     def step(events=None):
-        # stage 1 for all 8 instances (one launch), then stage 2 for all 8 (one launch)
-        B.factor_dense(A, stream=stream)
+        # pack + validate + factor + materialise all 8 instances: one launch
         if events is not None:
             events[0].record(stream)
-        B.enumerate(inst, zeros, counts, outs, 32, stream=stream)
+        B.solve(A, inst, zeros, counts, outs, 32, stream=stream)
         if events is not None:
             events[1].record(stream)
 
@@ -288,7 +288,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "batch_enum_kernel<uint32_t> (all 8 instances in one launch)",
+            "kernel": "batch_solve_kernel<uint32_t> (stage 1 + materialise of all 8 instances, one launch)",
             "achieved": round(achieved_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -248,6 +248,18 @@ hlf_status hlf_batch_enumerate(hlf_batch b, int32_t num, const int32_t *inst,
                                const uint64_t *begin, const uint64_t *count, void *const *out,
                                int32_t word_bits, hipStream_t stream);
 
+/* Stage 1 and stage 2 materialise in ONE launch, for instances with
+ * n_i <= word_bits <= 64: every listed instance is packed, validated and
+ * factored (its record written as by hlf_batch_factor_dense) and then
+ * out[k][i - begin[k]] = z_i for i in [begin[k], begin[k] + count[k]).
+ * The first workgroup of an instance factors it while the instance's other
+ * workgroups wait for that result.  1 <= num <= 16 tasks, each with count > 0,
+ * begin a multiple of 16 / (word_bits/8) and a 16-byte aligned out[k]
+ * (HLF_EINVAL otherwise).  Calls on one batch must be ordered (one stream).   */
+hlf_status hlf_batch_solve(hlf_batch b, const uint8_t *A_dev, int32_t num, const int32_t *inst,
+                           const uint64_t *begin, const uint64_t *count, void *const *out,
+                           int32_t word_bits, hipStream_t stream);
+
 /* Stage 1 + stage 2 reduce for the whole batch in ONE persistent launch (plus
  * one small launch that resets its work queue): wavefronts first take factor
  * tasks; every instance with rank <= max_rank (<= 62) then publishes its

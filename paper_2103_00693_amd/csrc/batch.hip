@@ -107,7 +107,7 @@ struct EnumTasks {
 
 template <typename T>
 __global__ __launch_bounds__(kTileThreads) void batch_enum_kernel(EnumTasks tasks) {
-    constexpr int S = Vec<T>::S;
+    constexpr int S = tile_shift<T>();
     __shared__ uint64_t Bx[64];
     int k = 0;
     for (int j = 1; j < tasks.num; ++j)
@@ -123,6 +123,93 @@ __global__ __launch_bounds__(kTileThreads) void batch_enum_kernel(EnumTasks task
     if (t0 >= ntiles) return;
     const uint64_t t1 = (t0 + t.tiles_per_block < ntiles) ? t0 + t.tiles_per_block : ntiles;
     enum_tiles_w1<T>(Bx, t.shift[0], t.begin, t.count, (T *)t.out, t0, t1);
+}
+
+// ---------------------------------------------------------------------------
+// Stage 1 + stage 2 materialise in one launch (instances with n <= 64).
+// The first workgroup of an instance to start claims its factorisation with a
+// CAS on flags[inst] (0 idle, 1 claimed, 2 done) and runs it on its first wave;
+// the instance's other workgroups wait for 2 -- a claim is only ever held by a
+// running workgroup, so every wait ends.  The last workgroup to finish resets
+// the flags of the launch, so each launch starts from idle flags.  Every
+// workgroup reaches the final counter (no early return).
+// ---------------------------------------------------------------------------
+struct SolveTasks {
+    EnumTask t[kMaxEnumTasks];
+    int32_t inst[kMaxEnumTasks];
+    int32_t num;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void batch_solve_kernel(BatchDev b,
+                                                                   const uint8_t *__restrict__ A,
+                                                                   SolveTasks tasks, int32_t *flags,
+                                                                   unsigned int *blocks_done) {
+    constexpr int S = tile_shift<T>();
+    __shared__ WaveSmem<1> sm;
+    __shared__ uint64_t Bx[64];
+    __shared__ int role;
+    __shared__ int ok;
+    __shared__ int rank_s;
+    const int tid = threadIdx.x;
+    int k = 0;
+    for (int j = 1; j < tasks.num; ++j)
+        if (tasks.t[j].block0 <= blockIdx.x) k = j;
+    const EnumTask &t = tasks.t[k];
+    const int i = tasks.inst[k];
+
+    if (tid == 0) {
+        int mine = 0;
+        if (__hip_atomic_load(&flags[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            int expected = 0;
+            mine = __hip_atomic_compare_exchange_strong(&flags[i], &expected, 1, __ATOMIC_ACQ_REL,
+                                                        __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+                       ? 1 : 0;
+        }
+        role = mine;
+    }
+    __syncthreads();
+    if (role) {
+        if (tid < 64) {
+            const int n = b.n[i];
+            const bool badv = wave_load_dense<1>(A + b.dense_off[i], n, 1, sm);
+            factor_wave_core<1>(n, 1, badv, record_of(b, i), sm);
+            __threadfence();
+            if (tid == 0) __hip_atomic_store(&flags[i], 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else if (tid == 0) {
+        while (__hip_atomic_load(&flags[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 2)
+            __builtin_amdgcn_s_sleep(2);
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the record written above / elsewhere
+    if (tid == 0) {
+        int r = 0;
+        ok = gate(t.status, t.rank, t.begin, t.count, r) ? 1 : 0;
+        rank_s = r;
+    }
+    __syncthreads();
+    if (ok) {
+        load_basis_padded<1>(t.basis, rank_s, Bx, tid, blockDim.x);
+        __syncthreads();
+        const uint64_t end = t.begin + t.count;
+        const uint64_t ntiles = ((end - 1) >> S) - (t.begin >> S) + 1;
+        const uint64_t t0 = (uint64_t)(blockIdx.x - t.block0) * t.tiles_per_block;
+        if (t0 < ntiles) {
+            const uint64_t t1 = (t0 + t.tiles_per_block < ntiles) ? t0 + t.tiles_per_block : ntiles;
+            enum_tiles_w1<T>(Bx, t.shift[0], t.begin, t.count, (T *)t.out, t0, t1);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        const unsigned int prev = atomicAdd(blocks_done, 1u);
+        if (prev == gridDim.x - 1) {
+            for (int j = 0; j < tasks.num; ++j)
+                __hip_atomic_store(&flags[tasks.inst[j]], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(blocks_done, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -310,6 +397,8 @@ struct hlf_batch_s {
     uint64_t *basis = nullptr, *shift = nullptr, *kernel = nullptr, *counts = nullptr, *hash = nullptr;
     uint64_t *rows = nullptr;  // packed rows of instances with n > 192
     int32_t *pack_status = nullptr;
+    int32_t *solve_flags = nullptr;        // per instance, idle between launches
+    unsigned int *solve_done = nullptr;    // workgroups finished in a solve launch
     hlf::QueueHead *queue = nullptr;
     hlf::ChunkSlot *slots = nullptr;
     hlf_batch_params tuned = {20, 8};
@@ -451,6 +540,8 @@ hlf_status hlf_batch_create(int32_t count, const int32_t *n_host, hlf_batch *out
     chk(dev_alloc(b, &b->hash, count));
     chk(dev_alloc(b, &b->rows, big_words));
     chk(dev_alloc(b, &b->pack_status, 1));
+    chk(dev_alloc(b, &b->solve_flags, count));
+    chk(dev_alloc(b, &b->solve_done, 1));
     chk(dev_alloc(b, &b->queue, 1));
     chk(dev_alloc(b, &b->slots, count));
     if (st == HLF_OK) {
@@ -465,6 +556,10 @@ hlf_status hlf_batch_create(int32_t count, const int32_t *n_host, hlf_batch *out
         up(b->d_order, b->order.data(), count * sizeof(int32_t));
         std::vector<int32_t> init(count, HLF_EINVAL);  // not factored yet
         up(b->status, init.data(), count * sizeof(int32_t));
+        std::vector<int32_t> zero(count, 0);
+        up(b->solve_flags, zero.data(), count * sizeof(int32_t));
+        const unsigned int zero_u = 0;
+        up(b->solve_done, &zero_u, sizeof(zero_u));
     }
     if (st != HLF_OK) {
         hlf_batch_destroy(b);
@@ -551,8 +646,8 @@ hlf_status hlf_batch_enumerate(hlf_batch b, int32_t num, const int32_t *inst,
         if (count[k] > 0 && !out[k]) return HLF_EINVAL;
     }
     const int V = 16 / (word_bits / 8);
-    const int S = word_bits == 16 ? hlf::Vec<uint16_t>::S
-                  : word_bits == 32 ? hlf::Vec<uint32_t>::S : hlf::Vec<uint64_t>::S;
+    const int S = word_bits == 16 ? hlf::tile_shift<uint16_t>()
+                  : word_bits == 32 ? hlf::tile_shift<uint32_t>() : hlf::tile_shift<uint64_t>();
     // Fast tasks go into multi-instance launches; the rest take the general path.
     std::vector<int> fast;
     for (int k = 0; k < num; ++k) {
@@ -567,7 +662,7 @@ hlf_status hlf_batch_enumerate(hlf_batch b, int32_t num, const int32_t *inst,
             if (s != HLF_OK) return s;
         }
     }
-    const uint64_t target_blocks = (uint64_t)hlf::device_cu_count() * 8;
+    const uint64_t target_blocks = (uint64_t)hlf::device_cu_count() * hlf::kTileBlocksPerCU;
     for (size_t g = 0; g < fast.size(); g += hlf::kMaxEnumTasks) {
         const size_t m = std::min<size_t>(hlf::kMaxEnumTasks, fast.size() - g);
         std::vector<uint64_t> tiles(m);
@@ -608,6 +703,59 @@ hlf_status hlf_batch_enumerate(hlf_batch b, int32_t num, const int32_t *inst,
         if (hipGetLastError() != hipSuccess) return HLF_EDEVICE;
     }
     return HLF_OK;
+}
+
+hlf_status hlf_batch_solve(hlf_batch b, const uint8_t *A_dev, int32_t num, const int32_t *inst,
+                           const uint64_t *begin, const uint64_t *count, void *const *out,
+                           int32_t word_bits, hipStream_t stream) {
+    if (!b || !A_dev || num < 1 || num > hlf::kMaxEnumTasks || !inst || !begin || !count || !out)
+        return HLF_EINVAL;
+    if (word_bits != 16 && word_bits != 32 && word_bits != 64) return HLF_EINVAL;
+    const int V = 16 / (word_bits / 8);
+    const int S = word_bits == 16 ? hlf::tile_shift<uint16_t>()
+                  : word_bits == 32 ? hlf::tile_shift<uint32_t>() : hlf::tile_shift<uint64_t>();
+    std::vector<uint64_t> tiles(num);
+    uint64_t total = 0;
+    for (int k = 0; k < num; ++k) {
+        const int i = inst[k];
+        if (i < 0 || i >= b->count || b->n[i] > word_bits) return HLF_EINVAL;
+        if (count[k] == 0 || !out[k] || begin[k] % V != 0 || ((uintptr_t)out[k] & 15u) != 0 ||
+            begin[k] + count[k] < begin[k])
+            return HLF_EINVAL;
+        const uint64_t end = begin[k] + count[k];
+        tiles[k] = ((end - 1) >> S) - (begin[k] >> S) + 1;
+        total += tiles[k];
+    }
+    const uint64_t target_blocks = (uint64_t)hlf::device_cu_count() * hlf::kTileBlocksPerCU;
+    const uint64_t tpb = std::max<uint64_t>(1, (total + target_blocks - 1) / target_blocks);
+    hlf::SolveTasks tasks;
+    std::memset(&tasks, 0, sizeof(tasks));
+    tasks.num = num;
+    uint64_t block = 0;
+    for (int k = 0; k < num; ++k) {
+        const int i = inst[k];
+        hlf::EnumTask &t = tasks.t[k];
+        t.status = b->status + i;
+        t.rank = b->rank + i;
+        t.basis = b->basis + b->mat_off[i];
+        t.shift = b->shift + b->vec_off[i];
+        t.out = out[k];
+        t.begin = begin[k];
+        t.count = count[k];
+        t.block0 = (uint32_t)block;
+        t.tiles_per_block = (uint32_t)tpb;
+        tasks.inst[k] = i;
+        block += (tiles[k] + tpb - 1) / tpb;
+    }
+    if (block > 0xFFFFFFFFull) return HLF_EINVAL;
+    const hlf::BatchDev d = view_of(b);
+    if (word_bits == 16)
+        hipLaunchKernelGGL(hlf::batch_solve_kernel<uint16_t>, dim3((unsigned)block), dim3(hlf::kTileThreads), 0, stream, d, A_dev, tasks, b->solve_flags, b->solve_done);
+    else if (word_bits == 32)
+        hipLaunchKernelGGL(hlf::batch_solve_kernel<uint32_t>, dim3((unsigned)block), dim3(hlf::kTileThreads), 0, stream, d, A_dev, tasks, b->solve_flags, b->solve_done);
+    else
+        hipLaunchKernelGGL(hlf::batch_solve_kernel<uint64_t>, dim3((unsigned)block), dim3(hlf::kTileThreads), 0, stream, d, A_dev, tasks, b->solve_flags, b->solve_done);
+    return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
 }
 
 hlf_status hlf_batch_reduce(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kTileThreads) void enum_tile_kernel(FactorIn f, uin
                                                                  uint64_t count,
                                                                  T *__restrict__ out,
                                                                  uint64_t tiles_per_block) {
-    constexpr int S = Vec<T>::S;
+    constexpr int S = tile_shift<T>();
     __shared__ uint64_t Bx[64];
     int r;
     if (!gate(f, begin, count, r)) return;
@@ -263,7 +263,7 @@ uint64_t tiles_per_block_for(uint64_t ntiles, uint64_t max_blocks, uint64_t *blo
 template <typename T>
 hlf_status launch_tile(const FactorIn &f, uint64_t begin, uint64_t count, T *out,
                        hipStream_t stream) {
-    constexpr int S = Vec<T>::S;
+    constexpr int S = tile_shift<T>();
     const uint64_t end = begin + count;  // host: may wrap only for invalid ranges
     uint64_t ntiles;
     if (end < begin) {
@@ -272,7 +272,8 @@ hlf_status launch_tile(const FactorIn &f, uint64_t begin, uint64_t count, T *out
         ntiles = ((end - 1) >> S) - (begin >> S) + 1;
     }
     uint64_t blocks;
-    const uint64_t tpb = tiles_per_block_for(ntiles, (uint64_t)device_cu_count() * 8, &blocks);
+    const uint64_t tpb =
+        tiles_per_block_for(ntiles, (uint64_t)device_cu_count() * kTileBlocksPerCU, &blocks);
     hipLaunchKernelGGL(enum_tile_kernel<T>, dim3((unsigned)blocks), dim3(kTileThreads), 0, stream,
                        f, begin, count, out, tpb);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;

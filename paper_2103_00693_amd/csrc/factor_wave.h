@@ -8,8 +8,8 @@
 // reduced rows then give the Ker(A) basis (task (2)), q on it (task (3)) and
 // the canonical shift (task (4)).
 //
-// Callers launch 64-thread workgroups (one wave), so __syncthreads below is a
-// single-wave barrier and an early return of the wave is safe.
+// Only the calling wave takes part (LDS ordering by wave_lds_sync), so the
+// routine can run on one wave of a larger workgroup.
 #pragma once
 
 #include "hlf_device.h"
@@ -79,7 +79,7 @@ __device__ int factor_wave_core(int n, int W, bool bad_input, const FactorOut &o
     const int lane = lane_id();
     if (lane < WMAX) sm.shiftw[lane] = 0;
     if (lane == 0) sm.internal = 0;
-    __syncthreads();
+    wave_lds_sync();
 
     uint64_t row[WMAX][WMAX];
     bool used[WMAX];
@@ -177,7 +177,7 @@ __device__ int factor_wave_core(int n, int W, bool bad_input, const FactorOut &o
 #pragma unroll
             for (int w = 0; w < WMAX; ++w)
                 if (w < W) sm.rref[rk[s] * W + w] = row[s][w];
-    __syncthreads();
+    wave_lds_sync();
 
     for (int k = lane; k < n; k += 64) out.pivots[k] = (k < r) ? sm.piv[k] : -1;
     for (int idx = lane; idx < r * W; idx += 64) {
@@ -215,7 +215,7 @@ __device__ int factor_wave_core(int n, int W, bool bad_input, const FactorOut &o
         if (q & 1u) sm.internal = 1;
         if (q & 2u) atomicOr(&sm.shiftw[f >> 6], 1ull << (f & 63));
     }
-    __syncthreads();
+    wave_lds_sync();
     if (lane < W) out.shift[lane] = sm.shiftw[lane];
     const bool internal = sm.internal != 0;
     if (lane == 0) {

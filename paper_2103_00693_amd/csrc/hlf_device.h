@@ -60,6 +60,15 @@ __device__ __forceinline__ uint64_t wave_xor_u64(uint64_t v) {
     return v;
 }
 
+// Orders the LDS accesses of one wavefront around this point (waits for its
+// outstanding LDS operations; no other wave is involved).  Used by code that
+// runs on a single wave of a larger workgroup.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
 // Mask of the valid bits of the last word of an n-bit vector (all ones when

@@ -84,24 +84,23 @@ __device__ __forceinline__ uint64_t tile_step(const uint64_t *Bx, uint64_t T, in
 // Materialise, W = 1, 16/32/64-bit words: V values per 16-byte store.
 // ---------------------------------------------------------------------------
 template <typename T>
-struct Vec;
-template <>
-struct Vec<uint16_t> {
-    static constexpr int V = 8;
-    static constexpr int S = 11;  // log2(256 * 8)
-};
-template <>
-struct Vec<uint32_t> {
-    static constexpr int V = 4;
-    static constexpr int S = 10;
-};
-template <>
-struct Vec<uint64_t> {
-    static constexpr int V = 2;
-    static constexpr int S = 9;
+struct Vec {
+    static constexpr int V = 16 / (int)sizeof(T);  // values per 16-byte store
+    static constexpr int LOGV = (V == 8) ? 3 : (V == 4) ? 2 : 1;
 };
 
-constexpr int kTileThreads = 256;
+// Materialise workgroups: 1024 threads, one 16-byte store per thread per
+// tile, so a tile holds 1024*V solutions.
+constexpr int kTileThreads = 1024;
+constexpr int kLogTileThreads = 10;
+// Workgroups per CU of a materialise launch (more workgroups than resident
+// slots: the dispatcher balances the tail).
+constexpr int kTileBlocksPerCU = 16;
+
+template <typename T>
+__host__ __device__ constexpr int tile_shift() {
+    return kLogTileThreads + Vec<T>::LOGV;
+}
 
 template <typename T>
 __device__ __forceinline__ void pack16(const uint64_t *v, uint32_t (&w)[4]) {
@@ -135,13 +134,13 @@ __device__ __forceinline__ void spread16(uint64_t h, uint32_t (&w)[4]) {
 }
 
 // Tiles [t0, t1) (relative to the first tile of [begin, begin+count)) of one
-// instance, by a 256-thread workgroup; out[i - begin] = z_i.  Requires
+// instance, by a kTileThreads workgroup; out[i - begin] = z_i.  Requires
 // begin % V == 0 and a 16-byte aligned `out`.  Bx: LDS basis (WW = 1).
 template <typename T>
 __device__ void enum_tiles_w1(const uint64_t *Bx, uint64_t l, uint64_t begin, uint64_t count,
                               T *__restrict__ out, uint64_t t0, uint64_t t1) {
     constexpr int V = Vec<T>::V;
-    constexpr int S = Vec<T>::S;
+    constexpr int S = tile_shift<T>();
     const int tid = threadIdx.x;
     uint64_t lo[V];
 #pragma unroll
@@ -172,11 +171,6 @@ __device__ void enum_tiles_w1(const uint64_t *Bx, uint64_t l, uint64_t begin, ui
         }
         hi ^= tile_step<1>(Bx, Tt, S, 0);
     }
-}
-
-template <typename T>
-__host__ __device__ constexpr int vec_shift() {
-    return Vec<T>::S;
 }
 
 // ---------------------------------------------------------------------------

@@ -232,3 +232,66 @@ def test_batch_config4_matches_plain_launches():
         _, h, _ = C.reduce_range(Fo, 0, 1 << Fo["rank"])
         assert hashes_b[i] == h, i
     B.close()
+
+
+@pytest.mark.parametrize("word_bits", [32, 64])
+def test_batch_solve_one_launch(word_bits):
+    mats = [grid_instance(5, seed=s) for s in CONFIG2_SEEDS]
+    Fs = [O.factor(m) for m in mats]
+    B = hlf.Batch([25] * len(mats))
+    A = B.dense_input(mats)
+    dt = torch.int32 if word_bits == 32 else torch.int64
+    counts = [1 << F["rank"] for F in Fs]
+    outs = [torch.empty(c, dtype=dt, device="cuda") for c in counts]
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-1)
+        print(f"[batch] solve wb={word_bits} rep={rep}", flush=True)
+        B.solve(A, list(range(8)), [0] * 8, counts, outs, word_bits)
+        torch.cuda.synchronize()
+        for s, (F, o) in enumerate(zip(Fs, outs)):
+            assert np.array_equal(narrow_to_u64(o), C.enumerate_range(F, 0, counts[s])[:, 0]), (rep, s)
+    recs = B.records()
+    for s, F in enumerate(Fs):
+        check_record(recs[s], F, f"solve record {s}")
+    # new matrices in the same input buffer: the next launch factors them again
+    mats2 = [mats[(s + 1) % 8] for s in range(8)]
+    A2 = B.dense_input(mats2)
+    A.copy_(A2)
+    counts2 = [counts[(s + 1) % 8] for s in range(8)]
+    outs2 = [torch.empty(c, dtype=dt, device="cuda") for c in counts2]
+    B.solve(A, list(range(8)), [0] * 8, counts2, outs2, word_bits)
+    torch.cuda.synchronize()
+    for s in range(8):
+        F = Fs[(s + 1) % 8]
+        assert np.array_equal(narrow_to_u64(outs2[s]), C.enumerate_range(F, 0, counts2[s])[:, 0]), s
+
+
+def test_batch_solve_partial_ranges_and_errors():
+    mats = [grid_instance(4, seed=0), grid_instance(5, seed=2), grid_instance(3, p=0.5, seed=4)]
+    Fs = [O.factor(m) for m in mats]
+    B = hlf.Batch([16, 25, 9])
+    A = B.dense_input(mats)
+    inst = [1, 0, 1, 2]
+    begin = [0, 8, 1 << 20, 0]
+    count = [1 << 20, (1 << Fs[0]["rank"]) - 8, 777, 1 << Fs[2]["rank"]]
+    outs = [torch.empty(c, dtype=torch.int32, device="cuda") for c in count]
+    print("[batch] solve partial", flush=True)
+    B.solve(A, inst, begin, count, outs, 32)
+    torch.cuda.synchronize()
+    for k in range(4):
+        ref = C.enumerate_range(Fs[inst[k]], begin[k], count[k])[:, 0]
+        assert np.array_equal(narrow_to_u64(outs[k]), ref), k
+    # out-of-range task: its instance gets HLF_ERANGE, the other instance is intact
+    o1 = torch.full((64,), -9, dtype=torch.int32, device="cuda")
+    o2 = torch.empty(1 << Fs[0]["rank"], dtype=torch.int32, device="cuda")
+    B.solve(A, [2, 0], [(1 << Fs[2]["rank"]) - 8, 0], [64, 1 << Fs[0]["rank"]], [o1, o2], 32)
+    st = B.statuses()
+    assert st[2] == hlf.HLF_ERANGE and st[0] == hlf.HLF_OK
+    assert bool((o1 == -9).all())
+    assert np.array_equal(narrow_to_u64(o2), C.enumerate_range(Fs[0], 0, 1 << Fs[0]["rank"])[:, 0])
+    # host-detected: n > word_bits, misaligned begin
+    with pytest.raises(hlf.HlfError):
+        B.solve(A, [1], [0], [16], [torch.empty(16, dtype=torch.int16, device="cuda")], 16)
+    with pytest.raises(hlf.HlfError):
+        B.solve(A, [0], [3], [16], [torch.empty(16, dtype=torch.int32, device="cuda")], 32)
