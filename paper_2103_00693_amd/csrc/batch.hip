@@ -158,12 +158,15 @@ __global__ __launch_bounds__(kTileThreads) void batch_solve_kernel(BatchDev b,
     const EnumTask &t = tasks.t[k];
     const int i = tasks.inst[k];
 
+    // Agent-scope acquire/release fences invalidate / write back the XCD's L2,
+    // so the claim and the wait use relaxed atomics and each workgroup takes
+    // exactly one acquire (thread 0) after it has seen the flag at 2.
     if (tid == 0) {
         int mine = 0;
-        if (__hip_atomic_load(&flags[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        if (__hip_atomic_load(&flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
             int expected = 0;
-            mine = __hip_atomic_compare_exchange_strong(&flags[i], &expected, 1, __ATOMIC_ACQ_REL,
-                                                        __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+            mine = __hip_atomic_compare_exchange_strong(&flags[i], &expected, 1, __ATOMIC_RELAXED,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                        ? 1 : 0;
         }
         role = mine;
@@ -174,15 +177,14 @@ __global__ __launch_bounds__(kTileThreads) void batch_solve_kernel(BatchDev b,
             const int n = b.n[i];
             const bool badv = wave_load_dense<1>(A + b.dense_off[i], n, 1, sm);
             factor_wave_core<1>(n, 1, badv, record_of(b, i), sm);
-            __threadfence();
             if (tid == 0) __hip_atomic_store(&flags[i], 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     } else if (tid == 0) {
-        while (__hip_atomic_load(&flags[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 2)
-            __builtin_amdgcn_s_sleep(2);
+        while (__hip_atomic_load(&flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 2)
+            __builtin_amdgcn_s_sleep(8);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the record written above / elsewhere
     if (tid == 0) {
         int r = 0;
         ok = gate(t.status, t.rank, t.begin, t.count, r) ? 1 : 0;
@@ -201,13 +203,16 @@ __global__ __launch_bounds__(kTileThreads) void batch_solve_kernel(BatchDev b,
         }
     }
     __syncthreads();
+    // Thread 0's flag accesses have all returned before its increment is
+    // issued, so the last workgroup can reset the flags; the end of the kernel
+    // makes the reset visible to the next launch.
     if (tid == 0) {
-        __threadfence();
-        const unsigned int prev = atomicAdd(blocks_done, 1u);
+        const unsigned int prev =
+            __hip_atomic_fetch_add(blocks_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == gridDim.x - 1) {
             for (int j = 0; j < tasks.num; ++j)
                 __hip_atomic_store(&flags[tasks.inst[j]], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(blocks_done, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(blocks_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
