@@ -248,6 +248,18 @@ hlf_status hlf_batch_enumerate(hlf_batch b, int32_t num, const int32_t *inst,
                                const uint64_t *begin, const uint64_t *count, void *const *out,
                                int32_t word_bits, hipStream_t stream);
 
+/* hlf_batch_enumerate for batch b, plus stage 1 (as hlf_batch_factor_dense)
+ * of every instance of another batch `next` (all n <= 64) from its dense
+ * input A_next_dev, carried by the same launch: extra workgroups factor
+ * `next` while the others materialise b.  Nothing in the launch reads the
+ * records it writes, so a pipeline alternates two batches: launch k
+ * materialises the instances factored by launch k-1 and factors those of
+ * launch k+1.  next must differ from b (HLF_EINVAL otherwise).               */
+hlf_status hlf_batch_enumerate_overlap(hlf_batch b, int32_t num, const int32_t *inst,
+                                       const uint64_t *begin, const uint64_t *count,
+                                       void *const *out, int32_t word_bits, hlf_batch next,
+                                       const uint8_t *A_next_dev, hipStream_t stream);
+
 /* Stage 1 and stage 2 materialise in ONE launch, for instances with
  * n_i <= word_bits <= 64: every listed instance is packed, validated and
  * factored (its record written as by hlf_batch_factor_dense) and then

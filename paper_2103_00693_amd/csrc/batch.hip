@@ -105,13 +105,43 @@ struct EnumTasks {
     int32_t num;
 };
 
-template <typename T>
-__global__ __launch_bounds__(kTileThreads) void batch_enum_kernel(EnumTasks tasks) {
+// Optional stage-1 work carried by a materialise launch: the first `blocks`
+// workgroups factor instances order[first .. first + num) of another batch,
+// one instance per wavefront (W = 1).  The records it writes are not read by
+// the same launch, so there is no dependency inside the launch.
+struct FactorJob {
+    BatchDev d;
+    const uint8_t *A;
+    int32_t first;
+    int32_t num;
+    uint32_t blocks;
+};
+
+constexpr int kWavesPerTileBlock = kTileThreads / 64;
+
+template <typename T, bool kFactor>
+__global__ __launch_bounds__(kTileThreads, 8) void batch_enum_kernel(EnumTasks tasks, FactorJob job) {
     constexpr int S = tile_shift<T>();
     __shared__ uint64_t Bx[64];
+    unsigned int bid = blockIdx.x;
+    if constexpr (kFactor) {
+        __shared__ WaveSmem<1> sm[kWavesPerTileBlock];
+        if (bid < job.blocks) {
+            const int w = threadIdx.x >> 6;
+            const int idx = (int)bid * kWavesPerTileBlock + w;
+            if (idx < job.num) {
+                const int i = job.d.order[job.first + idx];
+                const int n = job.d.n[i];
+                const bool badv = wave_load_dense<1>(job.A + job.d.dense_off[i], n, 1, sm[w]);
+                factor_wave_core<1>(n, 1, badv, record_of(job.d, i), sm[w]);
+            }
+            return;
+        }
+        bid -= job.blocks;
+    }
     int k = 0;
     for (int j = 1; j < tasks.num; ++j)
-        if (tasks.t[j].block0 <= blockIdx.x) k = j;
+        if (tasks.t[j].block0 <= bid) k = j;
     const EnumTask &t = tasks.t[k];
     int r;
     if (!gate(t.status, t.rank, t.begin, t.count, r)) return;
@@ -119,7 +149,7 @@ __global__ __launch_bounds__(kTileThreads) void batch_enum_kernel(EnumTasks task
     __syncthreads();
     const uint64_t end = t.begin + t.count;
     const uint64_t ntiles = ((end - 1) >> S) - (t.begin >> S) + 1;
-    const uint64_t t0 = (uint64_t)(blockIdx.x - t.block0) * t.tiles_per_block;
+    const uint64_t t0 = (uint64_t)(bid - t.block0) * t.tiles_per_block;
     if (t0 >= ntiles) return;
     const uint64_t t1 = (t0 + t.tiles_per_block < ntiles) ? t0 + t.tiles_per_block : ntiles;
     enum_tiles_w1<T>(Bx, t.shift[0], t.begin, t.count, (T *)t.out, t0, t1);
@@ -640,9 +670,25 @@ hlf_status hlf_batch_factor_dense(hlf_batch b, const uint8_t *A_dev, hipStream_t
     return HLF_OK;
 }
 
-hlf_status hlf_batch_enumerate(hlf_batch b, int32_t num, const int32_t *inst,
-                               const uint64_t *begin, const uint64_t *count, void *const *out,
-                               int32_t word_bits, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+void launch_enum_group(unsigned blocks, const hlf::EnumTasks &tasks, const hlf::FactorJob *job,
+                       hipStream_t stream) {
+    if (job) {
+        hipLaunchKernelGGL((hlf::batch_enum_kernel<T, true>), dim3(blocks + job->blocks),
+                           dim3(hlf::kTileThreads), 0, stream, tasks, *job);
+    } else {
+        hipLaunchKernelGGL((hlf::batch_enum_kernel<T, false>), dim3(blocks),
+                           dim3(hlf::kTileThreads), 0, stream, tasks, hlf::FactorJob{});
+    }
+}
+
+hlf_status batch_enumerate_impl(hlf_batch b, int32_t num, const int32_t *inst,
+                                const uint64_t *begin, const uint64_t *count, void *const *out,
+                                int32_t word_bits, const hlf::FactorJob *job, hipStream_t stream) {
     if (!b || num < 0 || (num > 0 && (!inst || !begin || !count || !out))) return HLF_EINVAL;
     if (word_bits != 16 && word_bits != 32 && word_bits != 64) return HLF_EINVAL;
     for (int k = 0; k < num; ++k) {
@@ -668,8 +714,9 @@ hlf_status hlf_batch_enumerate(hlf_batch b, int32_t num, const int32_t *inst,
         }
     }
     const uint64_t target_blocks = (uint64_t)hlf::device_cu_count() * hlf::kTileBlocksPerCU;
-    for (size_t g = 0; g < fast.size(); g += hlf::kMaxEnumTasks) {
-        const size_t m = std::min<size_t>(hlf::kMaxEnumTasks, fast.size() - g);
+    bool job_done = job == nullptr;
+    for (size_t g = 0; g < fast.size() || !job_done; g += hlf::kMaxEnumTasks) {
+        const size_t m = g < fast.size() ? std::min<size_t>(hlf::kMaxEnumTasks, fast.size() - g) : 0;
         std::vector<uint64_t> tiles(m);
         uint64_t total = 0;
         for (size_t j = 0; j < m; ++j) {
@@ -698,16 +745,39 @@ hlf_status hlf_batch_enumerate(hlf_batch b, int32_t num, const int32_t *inst,
             t.tiles_per_block = (uint32_t)tpb;
             block += (tiles[j] + tpb - 1) / tpb;
         }
-        if (block > 0xFFFFFFFFull) return HLF_EINVAL;
-        if (word_bits == 16)
-            hipLaunchKernelGGL(hlf::batch_enum_kernel<uint16_t>, dim3((unsigned)block), dim3(hlf::kTileThreads), 0, stream, tasks);
-        else if (word_bits == 32)
-            hipLaunchKernelGGL(hlf::batch_enum_kernel<uint32_t>, dim3((unsigned)block), dim3(hlf::kTileThreads), 0, stream, tasks);
-        else
-            hipLaunchKernelGGL(hlf::batch_enum_kernel<uint64_t>, dim3((unsigned)block), dim3(hlf::kTileThreads), 0, stream, tasks);
+        if (block > 0xFFFF0000ull) return HLF_EINVAL;
+        const hlf::FactorJob *jb = job_done ? nullptr : job;
+        job_done = true;
+        if (word_bits == 16) launch_enum_group<uint16_t>((unsigned)block, tasks, jb, stream);
+        else if (word_bits == 32) launch_enum_group<uint32_t>((unsigned)block, tasks, jb, stream);
+        else launch_enum_group<uint64_t>((unsigned)block, tasks, jb, stream);
         if (hipGetLastError() != hipSuccess) return HLF_EDEVICE;
     }
     return HLF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hlf_status hlf_batch_enumerate(hlf_batch b, int32_t num, const int32_t *inst,
+                               const uint64_t *begin, const uint64_t *count, void *const *out,
+                               int32_t word_bits, hipStream_t stream) {
+    return batch_enumerate_impl(b, num, inst, begin, count, out, word_bits, nullptr, stream);
+}
+
+hlf_status hlf_batch_enumerate_overlap(hlf_batch b, int32_t num, const int32_t *inst,
+                                       const uint64_t *begin, const uint64_t *count,
+                                       void *const *out, int32_t word_bits, hlf_batch next,
+                                       const uint8_t *A_next_dev, hipStream_t stream) {
+    if (!next || !A_next_dev || next == b || next->max_n > 64) return HLF_EINVAL;
+    hlf::FactorJob job;
+    job.d = view_of(next);
+    job.A = A_next_dev;
+    job.first = 0;
+    job.num = next->count;
+    job.blocks = (uint32_t)((next->count + hlf::kWavesPerTileBlock - 1) / hlf::kWavesPerTileBlock);
+    return batch_enumerate_impl(b, num, inst, begin, count, out, word_bits, &job, stream);
 }
 
 hlf_status hlf_batch_solve(hlf_batch b, const uint8_t *A_dev, int32_t num, const int32_t *inst,

@@ -42,13 +42,13 @@ __device__ __forceinline__ void wave_load_rows(const uint64_t *__restrict__ rows
 }
 
 // Dense row-major uint8 matrix into sm.orig: lane l reads column 64*w + l of
-// 32 rows at once (independent loads, one memory latency per group), and the
+// 16 rows at once (independent loads, one memory latency per group), and the
 // ballot over the 64 lanes of each row gives its packed word.  Returns true
 // on every lane if an entry is not 0/1.
 template <int WMAX>
 __device__ __forceinline__ bool wave_load_dense(const uint8_t *__restrict__ A, int n, int W,
                                                 WaveSmem<WMAX> &sm) {
-    constexpr int G = 32;
+    constexpr int G = 16;
     const int lane = lane_id();
     bool bad = false;
     for (int w = 0; w < W; ++w) {

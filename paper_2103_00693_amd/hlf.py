@@ -35,7 +35,7 @@ EXPORTED = (
     "hlf_version", "hlf_status_string", "hlf_words_for", "hlf_pack_dense", "hlf_factor",
     "hlf_factor_ex", "hlf_enumerate", "hlf_enumerate_reduce", "hlf_sample",
     "hlf_batch_create", "hlf_batch_destroy", "hlf_batch_get_layout", "hlf_batch_factor_dense",
-    "hlf_batch_enumerate", "hlf_batch_solve", "hlf_batch_reduce", "hlf_batch_tune", "hlf_batch_graph_capture",
+    "hlf_batch_enumerate", "hlf_batch_enumerate_overlap", "hlf_batch_solve", "hlf_batch_reduce", "hlf_batch_tune", "hlf_batch_graph_capture",
     "hlf_batch_graph_launch",
 )
 
@@ -302,6 +302,9 @@ def _batch_lib():
         L.hlf_batch_enumerate.restype = i32
         L.hlf_batch_enumerate.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), u64p, u64p,
                                           ctypes.POINTER(vp), i32, vp]
+        L.hlf_batch_enumerate_overlap.restype = i32
+        L.hlf_batch_enumerate_overlap.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), u64p,
+                                                  u64p, ctypes.POINTER(vp), i32, vp, vp, vp]
         L.hlf_batch_solve.restype = i32
         L.hlf_batch_solve.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int32), u64p, u64p,
                                       ctypes.POINTER(vp), i32, vp]
@@ -393,6 +396,19 @@ class Batch:
         oa = (ctypes.c_void_p * num)(*[o.data_ptr() for o in outs])
         _check(_batch_lib().hlf_batch_enumerate(self._h, num, ia, ba, ca, oa, word_bits,
                                                 _stream(stream)), "hlf_batch_enumerate")
+
+    def enumerate_overlap(self, inst, begin, count, outs, word_bits: int, next_batch: "Batch",
+                          A_next: torch.Tensor, stream=None):
+        """Materialise this batch's tasks and factor `next_batch` in the same launch."""
+        num = len(inst)
+        ia = (ctypes.c_int32 * num)(*[int(x) for x in inst])
+        ba = (ctypes.c_uint64 * num)(*[int(x) for x in begin])
+        ca = (ctypes.c_uint64 * num)(*[int(x) for x in count])
+        oa = (ctypes.c_void_p * num)(*[o.data_ptr() for o in outs])
+        _check(_batch_lib().hlf_batch_enumerate_overlap(self._h, num, ia, ba, ca, oa, word_bits,
+                                                        next_batch._h, _ptr(A_next),
+                                                        _stream(stream)),
+               "hlf_batch_enumerate_overlap")
 
     def solve(self, A_dev: torch.Tensor, inst, begin, count, outs, word_bits: int, stream=None):
         """Stage 1 + materialise of the listed instances in one launch."""

@@ -295,3 +295,29 @@ def test_batch_solve_partial_ranges_and_errors():
         B.solve(A, [1], [0], [16], [torch.empty(16, dtype=torch.int16, device="cuda")], 16)
     with pytest.raises(hlf.HlfError):
         B.solve(A, [0], [3], [16], [torch.empty(16, dtype=torch.int32, device="cuda")], 32)
+
+
+def test_batch_enumerate_overlap_pipeline():
+    mats = [grid_instance(5, seed=s) for s in CONFIG2_SEEDS[:4]] + [grid_instance(4, seed=1)]
+    Fs = [O.factor(m) for m in mats]
+    ns = [m.shape[0] for m in mats]
+    Bs = [hlf.Batch(ns), hlf.Batch(ns)]
+    A = Bs[0].dense_input(mats)
+    Bs[0].factor_dense(A)
+    counts = [1 << F["rank"] for F in Fs]
+    outs = [torch.empty(c, dtype=torch.int32, device="cuda") for c in counts]
+    refs = [C.enumerate_range(F, 0, c)[:, 0] for F, c in zip(Fs, counts)]
+    for k in range(4):
+        j = k % 2
+        for o in outs:
+            o.fill_(-1)
+        print(f"[batch] overlap step {k}", flush=True)
+        Bs[j].enumerate_overlap(list(range(5)), [0] * 5, counts, outs, 32, Bs[1 - j], A)
+        torch.cuda.synchronize()
+        for s, o in enumerate(outs):
+            assert np.array_equal(narrow_to_u64(o), refs[s]), (k, s)
+        recs = Bs[1 - j].records()  # factored by this launch
+        for s, F in enumerate(Fs):
+            check_record(recs[s], F, f"overlap step {k} instance {s}")
+    with pytest.raises(hlf.HlfError):
+        Bs[0].enumerate_overlap([0], [0], [16], [outs[0]], 32, Bs[0], A)
