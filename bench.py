@@ -92,6 +92,70 @@ def copy_calibration():
     print(f"copied {src.numel() * 8} bytes x3", flush=True)
 
 
+def tiny_mode(hlf, torch, stream, dev):
+    """N=4 grid (n = 16), all edges, seed 0: pack + factor + materialise all
+    2^r solutions as uint16 -- a latency measurement (a single launch chain)."""
+    from hlf_inputs import grid_instance
+
+    A = torch.from_numpy(grid_instance(4, seed=0)).to(dev)
+    rows = torch.empty((16, 1), dtype=torch.int64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    F = hlf.Factors(16, device=dev)
+    hlf.pack_dense(A, rows, st, stream=stream)
+    hlf.factor(rows, 16, F, stream=stream)
+    stream.synchronize()
+    r = int(F.rank.item())
+    out = torch.empty(1 << r, dtype=torch.int16, device=dev)
+    reps = 50
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    ms = []
+    for k in range(reps + 5):
+        e0.record(stream)
+        hlf.pack_dense(A, rows, st, stream=stream)
+        hlf.factor(rows, 16, F, stream=stream)
+        hlf.enumerate_solutions(F, 0, 1 << r, 16, out=out, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+        if k >= 5:
+            ms.append(e0.elapsed_time(e1))
+    F.check()
+    med = sorted(ms)[len(ms) // 2]
+    return {"workload": "N=4 grid (n=16), all edges, seed 0: pack + factor + materialise 2^r uint16",
+            "rank": r, "median_us": round(med * 1e3, 2),
+            "solutions_per_s_G": round((1 << r) / (med * 1e-3) / 1e9, 3)}
+
+
+def steady_mode(hlf, torch, stream, dev):
+    """Steady-state window of the materialise kernel: the full-rank n = 36
+    instance (N=6, all edges, b = 1^36, r = 36), indices [0, 2^30) as uint64
+    words (8 GiB written by one launch)."""
+    from hlf_inputs import grid_instance
+
+    A = torch.from_numpy(grid_instance(6, b="1" * 36)).to(dev)
+    rows, st = hlf.pack_dense(A, stream=stream)
+    F = hlf.factor(rows, 36, stream=stream)
+    count = 1 << 30
+    out = torch.empty(count, dtype=torch.int64, device=dev)
+    hlf.enumerate_solutions(F, 0, count, 64, out=out, stream=stream)
+    stream.synchronize()
+    F.check()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record(stream)
+    for _ in range(reps):
+        hlf.enumerate_solutions(F, 0, count, 64, out=out, stream=stream)
+    e1.record(stream)
+    stream.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / reps
+    del out
+    return {"workload": "N=6 grid (n=36), all edges, b=1^36 (r=36): solutions [0, 2^30) as uint64",
+            "kernel": "enum_tile_kernel<uint64_t>", "bytes": 8 * count,
+            "achieved_GBs": round(8 * count / s / 1e9, 1), "frac_of_8TBs": round(8 * count / s / 8e12, 4),
+            "solutions_per_s_G": round(count / s / 1e9, 1)}
+
+
 def batch_mode(hlf, torch, stream, dev):
     """4096 instances (N ~ U{3..12}, p ~ U{0.3, 0.5, 1.0}): factor every
     instance and reduce every instance with r <= 28.  Batched: the tuned
@@ -391,6 +455,8 @@ def main():
                            "rank": int(F.rank.item()), "samples_per_s": round(65536 / smp_s, 1),
                            "ms_per_65536": round(smp_s * 1e3, 4),
                            "factor_ms_n1024": round(fac_s * 1e3, 4)}
+        modes["tiny"] = tiny_mode(hlf, torch, stream, dev)
+        modes["steady"] = steady_mode(hlf, torch, stream, dev)
         modes["batch"] = batch_mode(hlf, torch, stream, dev)
         modes["serve"] = serve_mode(torch)
         result["modes"] = modes
