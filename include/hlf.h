@@ -156,6 +156,23 @@ hlf_status hlf_factor_ex(const uint64_t *rows_dev, const hlf_factors *f, uint32_
 hlf_status hlf_enumerate(const hlf_factors *f, uint64_t begin, uint64_t count,
                          int32_t word_bits, void *out_dev, hipStream_t stream);
 
+/* Stage 2 as the paper's circuit, evaluated literally (Section 2, Eqs. (1)-(2),
+ * Fig. 1(c)) in the binary-counter order of the FPGA design (Section 4):
+ * for i in [begin, begin + count), R carries bit k of i at the pivot position
+ * p_k and 0 elsewhere; y_v = XOR of R_u over the grid neighbours u of v, XOR
+ * b_v R_v (the four edge layers and the Toffoli layer); out[i - begin] =
+ * y XOR l (the final CNOT layer).  Equivalently z = l XOR (XOR over set bits
+ * k of i of B_k): the same solution set as hlf_enumerate in another order.
+ *   rows_dev  packed A (as for hlf_factor); A must be a subgraph of the
+ *             grid_N x grid_N grid, n = grid_N^2 <= 64, vertices row-major
+ *             (else HLF_EINVAL in f->status, nothing written).
+ *   word_bits 16/32/64 with n <= word_bits; begin a multiple of
+ *             16/(word_bits/8) and a 16-byte aligned out_dev (else HLF_EINVAL).
+ * Device errors as hlf_enumerate.                                               */
+hlf_status hlf_enumerate_circuit(const hlf_factors *f, const uint64_t *rows_dev, int32_t grid_N,
+                                 uint64_t begin, uint64_t count, int32_t word_bits, void *out_dev,
+                                 hipStream_t stream);
+
 /* Stage 2, reduce: over the solutions z_i, i in [begin, begin + count),
  *   counts_dev  dev uint64 [n]: counts[j] = number of solutions with bit j set;
  *   hash_dev    dev uint64 [1]: sum of h(z_i) mod 2^64;

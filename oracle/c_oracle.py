@@ -29,6 +29,9 @@ def lib():
         L.oracle_enumerate.restype = ctypes.c_int
         L.oracle_enumerate.argtypes = [u64p, ctypes.c_int, ctypes.c_int, u64p,
                                        ctypes.c_uint64, ctypes.c_uint64, u64p]
+        L.oracle_enumerate_counter.restype = ctypes.c_int
+        L.oracle_enumerate_counter.argtypes = [u64p, ctypes.c_int, ctypes.c_int, u64p,
+                                               ctypes.c_uint64, ctypes.c_uint64, u64p]
         L.oracle_reduce.restype = ctypes.c_int
         L.oracle_reduce.argtypes = [u64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, u64p,
                                     ctypes.c_uint64, ctypes.c_uint64, u64p, u64p, u64p]
@@ -67,6 +70,18 @@ def enumerate_range(F, begin: int, count: int) -> np.ndarray:
                                 _p(out) if count else _p(np.zeros(1, dtype=np.uint64)))
     if rc != 0:
         raise ValueError(f"oracle_enumerate failed ({rc})")
+    return out
+
+
+def enumerate_counter_range(F, begin: int, count: int) -> np.ndarray:
+    """uint64 array [count, W] of solutions begin .. begin+count-1 in counter order."""
+    basis, shift = _words(F)
+    W = F["words"]
+    out = np.zeros((count, W), dtype=np.uint64)
+    rc = lib().oracle_enumerate_counter(_p(basis), F["rank"], W, _p(shift), begin, count,
+                                        _p(out) if count else _p(np.zeros(1, dtype=np.uint64)))
+    if rc != 0:
+        raise ValueError(f"oracle_enumerate_counter failed ({rc})")
     return out
 
 

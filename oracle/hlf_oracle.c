@@ -81,6 +81,26 @@ int oracle_enumerate(const uint64_t *basis, int r, int W, const uint64_t *shift,
     return 0;
 }
 
+/* Counter order (the FPGA's binary counter, Section 4): solution number i is
+ * l XOR (XOR over k < r with bit k of i set of B_k), by the direct
+ * definition; out as oracle_enumerate. */
+int oracle_enumerate_counter(const uint64_t *basis, int r, int W, const uint64_t *shift,
+                             uint64_t begin, uint64_t count, uint64_t *out) {
+    if (r < 0 || r > 62 || W < 1 || W > 16) return -1;
+    if (begin > (1ULL << r) || count > (1ULL << r) - begin) return -3;
+    int64_t cnt = (int64_t)count;
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < cnt; ++t) {
+        const uint64_t i = begin + (uint64_t)t;
+        uint64_t *z = out + (size_t)t * W;
+        for (int w = 0; w < W; ++w) z[w] = shift[w];
+        for (int k = 0; k < r; ++k)
+            if ((i >> k) & 1ULL)
+                for (int w = 0; w < W; ++w) z[w] ^= basis[(size_t)k * W + w];
+    }
+    return 0;
+}
+
 /* counts[j] = #solutions with bit j set (j < n); *hash = sum of h(z);
  * xorfold[w] = XOR of all solutions (may be NULL). */
 int oracle_reduce(const uint64_t *basis, int r, int W, int n, const uint64_t *shift,

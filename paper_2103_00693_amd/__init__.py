@@ -11,6 +11,7 @@ from .hlf import (  # noqa: F401
     Factors,
     HlfError,
     as_uint64,
+    enumerate_circuit,
     enumerate_reduce,
     enumerate_solutions,
     factor,

@@ -112,6 +112,118 @@ __global__ __launch_bounds__(256) void enum_general_kernel(FactorIn f, uint64_t 
 }
 
 // ---------------------------------------------------------------------------
+// The paper's circuit, evaluated literally (Section 2, Eqs. (1)-(2), Fig. 1(c))
+// and fed by the binary counter of the FPGA design (Section 4).  Solution
+// number i:
+//   R = the bits of i scattered onto the pivot positions (R_{p_k} = bit k),
+//   y = ((R & H) << 1) ^ ((R >> 1) & H)        horizontal-edge ROU layers
+//     ^ ((R & Vm) << N) ^ ((R >> N) & Vm)      vertical-edge ROU layers
+//     ^ (R & b)                                Toffoli layer (colours b)
+//   z = y ^ l                                  final CNOT layer
+// H has bit v set when the edge (v, v+1) exists, Vm when (v, v+N) exists.
+// The scatter is linear in the bits of i, so R = R_lo(x) ^ R_hi(T) for
+// i = (T << S) | x; the circuit itself runs for every solution.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void circuit_tile_kernel(
+    FactorIn f, const int32_t *__restrict__ pivots, const uint64_t *__restrict__ rows, int N,
+    uint64_t begin, uint64_t count, T *__restrict__ out, uint64_t tiles_per_block) {
+    constexpr int V = Vec<T>::V;
+    constexpr int S = tile_shift<T>();
+    __shared__ uint64_t PM[65];  // PM[k] = OR of e_{p_j}, j < min(k, r)
+    __shared__ uint64_t masks[3];
+    __shared__ int grid_ok;
+    int r;
+    if (!gate(f, begin, count, r)) return;
+    const int tid = threadIdx.x;
+    const int n = f.n;
+    if (tid < 64) {
+        const int v = tid;
+        const uint64_t row = (v < n) ? rows[v] : 0ull;
+        const int gr = v / N, gc = v - (v / N) * N;
+        uint64_t allowed = 0;
+        if (v < n) {
+            allowed |= 1ull << v;
+            if (gc > 0) allowed |= 1ull << (v - 1);
+            if (gc < N - 1) allowed |= 1ull << (v + 1);
+            if (gr > 0) allowed |= 1ull << (v - N);
+            if (gr < N - 1) allowed |= 1ull << (v + N);
+        }
+        const bool off_grid = (row & ~allowed) != 0;
+        const uint64_t H = __ballot(v < n && gc < N - 1 && ((row >> (v + 1)) & 1ull));
+        const uint64_t Vm = __ballot(v < n && gr < N - 1 && ((row >> (v + N)) & 1ull));
+        const uint64_t bb = __ballot(v < n && ((row >> v) & 1ull));
+        const bool any_off = __ballot(off_grid) != 0;
+        if (tid == 0) {
+            masks[0] = H;
+            masks[1] = Vm;
+            masks[2] = bb;
+            grid_ok = any_off ? 0 : 1;
+            uint64_t acc = 0;
+            PM[0] = 0;
+            for (int k = 0; k < 64; ++k) {
+                if (k < r) acc |= 1ull << pivots[k];
+                PM[k + 1] = acc;
+            }
+        }
+    }
+    __syncthreads();
+    if (!grid_ok) {
+        if (tid == 0) *f.status = HLF_EINVAL;
+        return;
+    }
+    const uint64_t H = masks[0], Vm = masks[1], bb = masks[2];
+    const uint64_t l = f.shift[0];
+    uint64_t Rlo[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const uint64_t x = (uint64_t)(tid * V + e);
+        uint64_t R = 0;
+        for (int j = 0; j < S; ++j)
+            if ((x >> j) & 1ull) R ^= PM[j + 1] ^ PM[j];
+        Rlo[e] = R;
+    }
+    const uint64_t end = begin + count;
+    const uint64_t ntiles = ((end - 1) >> S) - (begin >> S) + 1;
+    const uint64_t t0 = (uint64_t)blockIdx.x * tiles_per_block;
+    if (t0 >= ntiles) return;
+    const uint64_t t1 = (t0 + tiles_per_block < ntiles) ? t0 + tiles_per_block : ntiles;
+    uint64_t Tt = (begin >> S) + t0;
+    uint64_t Rhi = 0;
+    for (int j = 0; j + S < 64 && (Tt >> j); ++j)
+        if ((Tt >> j) & 1ull) Rhi ^= PM[S + j + 1] ^ PM[S + j];
+    for (uint64_t t = t0; t < t1; ++t, ++Tt) {
+        uint64_t zv[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const uint64_t R = Rlo[e] ^ Rhi;
+            const uint64_t y = ((R & H) << 1) ^ ((R >> 1) & H) ^ ((R & Vm) << N) ^
+                               ((R >> N) & Vm) ^ (R & bb);
+            zv[e] = y ^ l;
+        }
+        const uint64_t i0 = (Tt << S) + (uint64_t)(tid * V);
+        if (i0 >= begin && i0 + V <= end) {
+            uint32_t w[4];
+            pack16<T>(zv, w);
+            u32x4 val;
+            val.x = w[0];
+            val.y = w[1];
+            val.z = w[2];
+            val.w = w[3];
+            __builtin_nontemporal_store(val, (u32x4 *)(out + (i0 - begin)));
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const uint64_t i = i0 + e;
+                if (i >= begin && i < end) out[i - begin] = (T)zv[e];
+            }
+        }
+        const int c = S + __builtin_ctzll(Tt + 1) + 1;
+        Rhi ^= PM[c < 64 ? c : 64] ^ PM[S];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Reduce, W <= 3: 4 waves per block, each on a contiguous range of tiles.
 // ---------------------------------------------------------------------------
 template <int WW>
@@ -345,6 +457,26 @@ hlf_status launch_enumerate(const FactorIn &f, uint64_t begin, uint64_t count, i
     if (W <= 4) return launch_general<4, uint64_t>(f, begin, count, o, stream);
     if (W <= 8) return launch_general<8, uint64_t>(f, begin, count, o, stream);
     return launch_general<16, uint64_t>(f, begin, count, o, stream);
+}
+
+hlf_status launch_circuit(const FactorIn &f, const int32_t *pivots, const uint64_t *rows, int N,
+                          uint64_t begin, uint64_t count, int word_bits, void *out,
+                          hipStream_t stream) {
+    const uint64_t end = begin + count;
+    auto go = [&](auto tag) -> hlf_status {
+        using T = decltype(tag);
+        constexpr int S = tile_shift<T>();
+        const uint64_t ntiles = (end < begin) ? 1 : ((end - 1) >> S) - (begin >> S) + 1;
+        uint64_t blocks;
+        const uint64_t tpb =
+            tiles_per_block_for(ntiles, (uint64_t)device_cu_count() * kTileBlocksPerCU, &blocks);
+        hipLaunchKernelGGL(circuit_tile_kernel<T>, dim3((unsigned)blocks), dim3(kTileThreads), 0,
+                           stream, f, pivots, rows, N, begin, count, (T *)out, tpb);
+        return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
+    };
+    if (word_bits == 16) return go(uint16_t{});
+    if (word_bits == 32) return go(uint32_t{});
+    return go(uint64_t{});
 }
 
 hlf_status launch_reduce(const FactorIn &f, uint64_t begin, uint64_t count, bool accumulate,

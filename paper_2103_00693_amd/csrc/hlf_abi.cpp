@@ -109,6 +109,20 @@ hlf_status hlf_enumerate(const hlf_factors *f, uint64_t begin, uint64_t count, i
     return hlf::launch_enumerate(view(f), begin, count, word_bits, out_dev, stream);
 }
 
+hlf_status hlf_enumerate_circuit(const hlf_factors *f, const uint64_t *rows_dev, int32_t grid_N,
+                                 uint64_t begin, uint64_t count, int32_t word_bits, void *out_dev,
+                                 hipStream_t stream) {
+    if (!record_ok(f) || !rows_dev) return HLF_EINVAL;
+    if (f->words != 1 || grid_N < 1 || grid_N * grid_N != f->n) return HLF_EINVAL;
+    if ((word_bits != 16 && word_bits != 32 && word_bits != 64) || f->n > word_bits)
+        return HLF_EINVAL;
+    if (count == 0) return HLF_OK;
+    const uint64_t V = 16 / (uint64_t)(word_bits / 8);
+    if (!out_dev || ((uintptr_t)out_dev & 15u) != 0 || begin % V != 0) return HLF_EINVAL;
+    return hlf::launch_circuit(view(f), f->pivots, rows_dev, grid_N, begin, count, word_bits,
+                               out_dev, stream);
+}
+
 hlf_status hlf_enumerate_reduce(const hlf_factors *f, uint64_t begin, uint64_t count,
                                 uint32_t flags, uint64_t *counts_dev, uint64_t *hash_dev,
                                 uint64_t *xorfold_dev, hipStream_t stream) {

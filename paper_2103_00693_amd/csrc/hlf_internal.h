@@ -36,6 +36,9 @@ hlf_status launch_factor(const uint64_t *rows, int n, int W, const FactorOut &ou
                          bool force_workgroup, hipStream_t stream);
 hlf_status launch_enumerate(const FactorIn &f, uint64_t begin, uint64_t count, int word_bits,
                             void *out, hipStream_t stream);
+hlf_status launch_circuit(const FactorIn &f, const int32_t *pivots, const uint64_t *rows, int N,
+                          uint64_t begin, uint64_t count, int word_bits, void *out,
+                          hipStream_t stream);
 hlf_status launch_reduce(const FactorIn &f, uint64_t begin, uint64_t count, bool accumulate,
                          uint64_t *counts, uint64_t *hash, uint64_t *xorfold,
                          hipStream_t stream);

@@ -33,7 +33,8 @@ HLF_FACTOR_WORKGROUP = 1
 
 EXPORTED = (
     "hlf_version", "hlf_status_string", "hlf_words_for", "hlf_pack_dense", "hlf_factor",
-    "hlf_factor_ex", "hlf_enumerate", "hlf_enumerate_reduce", "hlf_sample",
+    "hlf_factor_ex", "hlf_enumerate", "hlf_enumerate_circuit", "hlf_enumerate_reduce",
+    "hlf_sample",
     "hlf_batch_create", "hlf_batch_destroy", "hlf_batch_get_layout", "hlf_batch_factor_dense",
     "hlf_batch_enumerate", "hlf_batch_enumerate_overlap", "hlf_batch_solve", "hlf_batch_reduce", "hlf_batch_tune", "hlf_batch_graph_capture",
     "hlf_batch_graph_launch",
@@ -86,6 +87,8 @@ def lib():
         L.hlf_factor_ex.argtypes = [vp, fp, u32, vp]
         L.hlf_enumerate.restype = i32
         L.hlf_enumerate.argtypes = [fp, u64, u64, i32, vp, vp]
+        L.hlf_enumerate_circuit.restype = i32
+        L.hlf_enumerate_circuit.argtypes = [fp, vp, i32, u64, u64, i32, vp, vp]
         L.hlf_enumerate_reduce.restype = i32
         L.hlf_enumerate_reduce.argtypes = [fp, u64, u64, u32, vp, vp, vp, vp]
         L.hlf_sample.restype = i32
@@ -217,6 +220,17 @@ def enumerate_solutions(F: Factors, begin: int, count: int, word_bits: int,
             out = torch.empty((count, word_bits // 64), dtype=torch.int64, device=F.device)
     _check(lib().hlf_enumerate(F.c, begin, count, word_bits, _ptr(out) if count else None,
                                _stream(stream)), "hlf_enumerate")
+    return out
+
+
+def enumerate_circuit(F: Factors, rows: torch.Tensor, grid_N: int, begin: int, count: int,
+                      word_bits: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """f1: hlf_enumerate_circuit -- the paper's circuit in binary-counter order."""
+    if out is None:
+        out = torch.empty(count, dtype=_DTYPES[word_bits], device=F.device)
+    _check(lib().hlf_enumerate_circuit(F.c, _ptr(rows), grid_N, begin, count, word_bits,
+                                       _ptr(out) if count else None, _stream(stream)),
+           "hlf_enumerate_circuit")
     return out
 
 

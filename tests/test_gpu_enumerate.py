@@ -186,3 +186,82 @@ def test_invalid_matrix_propagates_status():
     torch.cuda.synchronize()
     assert bool((out == -3).all())
     assert int(F.status.item()) == hlf.HLF_ENOTSYM
+
+
+# -- the paper's circuit in counter order (hlf_enumerate_circuit) ----------------
+
+def gpu_rows(A):
+    from gpu_util import device_matrix
+    rows, _ = hlf.pack_dense(device_matrix(A))
+    return rows
+
+
+@pytest.mark.parametrize("seed", CONFIG2_SEEDS)
+def test_circuit_counter_order_config2(seed):
+    A = grid_instance(5, seed=seed)
+    Fo = O.factor(A)
+    r = Fo["rank"]
+    F, _ = gpu_factor(A)
+    print(f"[circuit] config2 seed={seed} r={r}", flush=True)
+    out = hlf.enumerate_circuit(F, gpu_rows(A), 5, 0, 1 << r, 32)
+    torch.cuda.synchronize()
+    assert int(F.status.item()) == hlf.HLF_OK
+    got = narrow_to_u64(out)
+    assert np.array_equal(got, C.enumerate_counter_range(Fo, 0, 1 << r)[:, 0])
+    if seed == 0:  # same set as the Gray-order materialisation
+        gray = narrow_to_u64(gpu_enum(F, 0, 1 << r, 32))
+        assert np.array_equal(np.sort(got), np.sort(gray))
+
+
+@pytest.mark.parametrize("name,N,A", [
+    ("2x2 b=1011", 2, grid_instance(2, b="1011")),
+    ("3x3 p=0.5", 3, grid_instance(3, p=0.5, seed=2)),
+    ("4x4 paper 0^15 1", 4, grid_instance(4, b="0" * 15 + "1")),
+    ("8x8 p=0.5", 8, grid_instance(8, p=0.5, seed=5)),
+])
+def test_circuit_matches_literal_python_circuit(name, N, A):
+    Fo = O.factor(A)
+    r = Fo["rank"]
+    F, _ = gpu_factor(A)
+    n = N * N
+    wb = 16 if n <= 16 else 32 if n <= 32 else 64
+    count = min(1 << r, 2000)
+    print(f"[circuit] {name} r={r}", flush=True)
+    out = hlf.enumerate_circuit(F, gpu_rows(A), N, 0, count, wb)
+    torch.cuda.synchronize()
+    assert [int(v) for v in narrow_to_u64(out)] == O.enumerate_counter_order(A, Fo, 0, count)
+    if r > 14:
+        b0 = ((1 << r) - 4096) & ~7
+        out2 = hlf.enumerate_circuit(F, gpu_rows(A), N, b0, 4096, wb)
+        torch.cuda.synchronize()
+        assert np.array_equal(narrow_to_u64(out2), C.enumerate_counter_range(Fo, b0, 4096)[:, 0])
+
+
+def test_circuit_ragged_ranges():
+    A = grid_instance(5, seed=1)
+    Fo = O.factor(A)
+    r = Fo["rank"]
+    F, _ = gpu_factor(A)
+    rows = gpu_rows(A)
+    for begin, count in [(0, 1), (4, 4095), (8, 4096 * 5 + 3), ((1 << r) - 12, 12), (1 << 20, (1 << 20) + 5)]:
+        print(f"[circuit] ragged begin={begin} count={count}", flush=True)
+        out = hlf.enumerate_circuit(F, rows, 5, begin, count, 32)
+        torch.cuda.synchronize()
+        assert np.array_equal(narrow_to_u64(out), C.enumerate_counter_range(Fo, begin, count)[:, 0])
+
+
+def test_circuit_rejects_non_grid_and_bad_arguments():
+    A = grid_instance(3, p=1.0, seed=0)
+    A[0, 5] = A[5, 0] = 1  # an edge that is not a grid edge
+    F, st = gpu_factor(A)
+    assert st == hlf.HLF_OK and int(F.status.item()) == hlf.HLF_OK
+    out = torch.full((16,), -4, dtype=torch.int16, device="cuda")
+    hlf.enumerate_circuit(F, gpu_rows(A), 3, 0, 16, 16, out=out)
+    torch.cuda.synchronize()
+    assert int(F.status.item()) == hlf.HLF_EINVAL
+    assert bool((out == -4).all())
+    G, _ = gpu_factor(grid_instance(3, seed=1))
+    with pytest.raises(hlf.HlfError):
+        hlf.enumerate_circuit(G, gpu_rows(grid_instance(3, seed=1)), 4, 0, 16, 16)  # N^2 != n
+    with pytest.raises(hlf.HlfError):
+        hlf.enumerate_circuit(G, gpu_rows(grid_instance(3, seed=1)), 3, 3, 16, 16)  # begin % 8

@@ -348,3 +348,17 @@ def test_c_oracle_counts_closed_form_at_scale():
     for j in range(25):
         assert int(counts[j]) == ((1 << (r - 1)) if A[j].any() else 0)
     assert int(xf[0]) == 0
+
+
+def test_c_oracle_counter_order_equals_literal_circuit():
+    """The C counter-order enumerator equals the paper's circuit (Eqs. (1)-(2)
+    evaluated layer by layer, Fig. 1(c)) fed by the binary counter (Section 4)."""
+    for seed, (N, p) in enumerate([(3, 1.0), (4, 0.5), (5, 1.0), (4, 1.0)]):
+        A = grid_instance(N, p=p, seed=seed)
+        F = O.factor(A)
+        total = 1 << F["rank"]
+        for begin, count in [(0, min(total, 300)), (max(0, total - 77), min(total, 77))]:
+            got = [int(z[0]) for z in C.enumerate_counter_range(F, begin, count)]
+            assert got == O.enumerate_counter_order(A, F, begin, count)
+        assert set(int(z[0]) for z in C.enumerate_counter_range(F, 0, min(total, 1 << 12))) <= \
+            set(int(z[0]) for z in C.enumerate_range(F, 0, total))
