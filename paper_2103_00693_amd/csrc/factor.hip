@@ -6,8 +6,8 @@
 //     lane keeps its rows in VGPRs, pivots are found with a ballot and the
 //     pivot row is broadcast with readlane -- no barriers in the elimination;
 //   * factor_workgroup_kernel: one workgroup per instance for n <= 1024, one
-//     row per thread in VGPRs, pivot choice by an LDS atomicMin over per-wave
-//     ballots, the pivot row broadcast through LDS.
+//     row per thread (VGPRs, mirrored in LDS), pivot choice by an LDS
+//     atomicMin over per-wave ballots, one barrier per column.
 // Both variants produce the canonical record defined in hlf.h (the RREF is
 // unique, so the pivot rows chosen do not matter).
 #include "factor_wave.h"
@@ -98,7 +98,6 @@ template <int WMAX>
 __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *__restrict__ rows,
                                                                 int n, int W, FactorOut out) {
     __shared__ uint64_t mat[64 * WMAX * WMAX];
-    __shared__ uint64_t prow[WMAX];
     __shared__ int piv[64 * WMAX];
     __shared__ int freec[64 * WMAX];
     __shared__ int qacc[64 * WMAX];
@@ -150,44 +149,62 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
         return;
     }
 
+    // Gauss-Jordan with one barrier per column.  `mat` holds every current row
+    // (row i at i*W, kept equal to thread i's registers).  Phase c: every
+    // thread reads the pivot p of column c chosen before the barrier, XORs row
+    // p (read from LDS) into its own row if it has bit c, stores its row back,
+    // and offers itself as a candidate for column c+1 (atomicMin over
+    // per-wave ballots).  Row p is not written in phase c, so all reads of it
+    // see one value; a candidate slot is reset two columns before its reuse,
+    // after every thread has read it.
     int r = 0, nfree = 0, slot = 0;
     bool used = false;
     int myk = -1;
+    {
+        const uint64_t m = __ballot(tid < n && (row[0] & 1ull));
+        if (lane == 0 && m) atomicMin(&cand[0], wave * 64 + __builtin_ctzll(m));
+    }
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        const int p = cand[slot];
+        if (tid == 0) cand[slot == 0 ? 2 : slot - 1] = INT_MAX;
+        const int cw = c >> 6, cb = c & 63;
+        if (p != INT_MAX) {
+            uint64_t word = 0;
 #pragma unroll
-    for (int cw = 0; cw < WMAX; ++cw) {
-        if (cw >= W) break;
-        for (int cb = 0; cb < 64; ++cb) {
-            const int c = 64 * cw + cb;
-            if (c >= n) break;
-            const bool hit = (row[cw] >> cb) & 1ull;
-            const uint64_t m = __ballot(tid < n && !used && hit);
-            if (lane == 0 && m) atomicMin(&cand[slot], wave * 64 + __builtin_ctzll(m));
-            __syncthreads();
-            const int p = cand[slot];
-            // The slot of column c+2 was last read during column c-1, which
-            // every thread finished before the barrier above.
-            if (tid == 0) cand[slot == 0 ? 2 : slot - 1] = INT_MAX;
-            slot = (slot == 2) ? 0 : slot + 1;
-            if (p == INT_MAX) {
-                if (tid == 0) freec[nfree] = c;
-                ++nfree;
-                continue;
-            }
+            for (int w = 0; w < WMAX; ++w)
+                if (w == cw) word = row[w];
             if (tid == p) {
-#pragma unroll
-                for (int w = 0; w < WMAX; ++w) prow[w] = row[w];
                 used = true;
                 myk = r;
             }
             if (tid == 0) piv[r] = c;
-            __syncthreads();
-            if (hit && tid != p) {
+            if (((word >> cb) & 1ull) && tid != p) {
+                const uint64_t *prow_l = &mat[p * W];
 #pragma unroll
                 for (int w = 0; w < WMAX; ++w)
-                    if (w < W) row[w] ^= prow[w];
+                    if (w < W) {
+                        row[w] ^= prow_l[w];
+                        mat[tid * W + w] = row[w];
+                    }
             }
             ++r;
+        } else {
+            if (tid == 0) freec[nfree] = c;
+            ++nfree;
         }
+        const int nslot = (slot == 2) ? 0 : slot + 1;
+        if (c + 1 < n) {
+            const int c1 = c + 1;
+            uint64_t word1 = 0;
+#pragma unroll
+            for (int w = 0; w < WMAX; ++w)
+                if (w == (c1 >> 6)) word1 = row[w];
+            const uint64_t m = __ballot(tid < n && !used && ((word1 >> (c1 & 63)) & 1ull));
+            if (lane == 0 && m) atomicMin(&cand[nslot], wave * 64 + __builtin_ctzll(m));
+        }
+        slot = nslot;
+        __syncthreads();
     }
     __syncthreads();
     if (used)

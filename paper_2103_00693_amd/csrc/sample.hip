@@ -14,15 +14,20 @@
 namespace hlf {
 namespace {
 
+// A sample's W words are split over TPS threads (at most 4 words each), so
+// that large-n launches still spread over every CU.
 template <int WMAX>
 struct SampleShape {
     static constexpr int kThreads = (WMAX >= 8) ? 1024 : 256;
+    static constexpr int kTPS = (WMAX + 3) / 4;            // threads per sample
+    static constexpr int kWPT = (WMAX + kTPS - 1) / kTPS;  // words per thread
 };
 
 template <int WMAX>
 __global__ __launch_bounds__(SampleShape<WMAX>::kThreads) void sample_kernel(
     FactorIn f, uint64_t seed, uint64_t num, const uint64_t *__restrict__ coeffs,
     uint64_t *__restrict__ out) {
+    using Sh = SampleShape<WMAX>;
     __shared__ uint64_t Bs[64 * WMAX * WMAX];
     __shared__ uint64_t ls[WMAX];
     if (*(volatile int32_t *)f.status != HLF_OK) return;
@@ -33,34 +38,40 @@ __global__ __launch_bounds__(SampleShape<WMAX>::kThreads) void sample_kernel(
     __syncthreads();
 
     const int R64 = (r + 63) >> 6;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < num; s += stride) {
-        uint64_t z[WMAX];
+    const int g = (int)threadIdx.x % Sh::kTPS;  // word group of this thread
+    const int w0 = g * Sh::kWPT;
+    const uint64_t per_block = blockDim.x / Sh::kTPS;
+    const uint64_t stride = (uint64_t)gridDim.x * per_block;
+    for (uint64_t s = (uint64_t)blockIdx.x * per_block + threadIdx.x / Sh::kTPS; s < num;
+         s += stride) {
+        uint64_t z[Sh::kWPT];
 #pragma unroll
-        for (int w = 0; w < WMAX; ++w) z[w] = (w < W) ? ls[w] : 0ull;
+        for (int q = 0; q < Sh::kWPT; ++q) z[q] = (w0 + q < W) ? ls[w0 + q] : 0ull;
         for (int kw = 0; kw < R64; ++kw) {
             const uint64_t ctr = s * (uint64_t)R64 + (uint64_t)kw;
             const uint64_t c = coeffs ? coeffs[ctr] : mix13(seed + (ctr + 1) * kGamma);
             const int nb = (r - 64 * kw) < 64 ? (r - 64 * kw) : 64;
-            const uint64_t *B = &Bs[(size_t)(64 * kw) * W];
+            const uint64_t *B = &Bs[(size_t)(64 * kw) * W + w0];
             for (int kb = 0; kb < nb; ++kb) {
                 const uint64_t mask = 0ull - ((c >> kb) & 1ull);
 #pragma unroll
-                for (int w = 0; w < WMAX; ++w)
-                    if (w < W) z[w] ^= B[kb * W + w] & mask;
+                for (int q = 0; q < Sh::kWPT; ++q)
+                    if (w0 + q < W) z[q] ^= B[kb * W + q] & mask;
             }
         }
 #pragma unroll
-        for (int w = 0; w < WMAX; ++w)
-            if (w < W) out[s * W + w] = z[w];
+        for (int q = 0; q < Sh::kWPT; ++q)
+            if (w0 + q < W) out[s * W + w0 + q] = z[q];
     }
 }
 
 template <int WMAX>
 hlf_status launch_sample_t(const FactorIn &f, uint64_t seed, uint64_t num,
                            const uint64_t *coeffs, uint64_t *out, hipStream_t stream) {
-    constexpr int T = SampleShape<WMAX>::kThreads;
-    uint64_t blocks = (num + T - 1) / T;
+    using Sh = SampleShape<WMAX>;
+    constexpr int T = Sh::kThreads;
+    const uint64_t per_block = T / Sh::kTPS;
+    uint64_t blocks = (num + per_block - 1) / per_block;
     const uint64_t cap = (uint64_t)device_cu_count() * ((WMAX >= 8) ? 1 : 4);
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
