@@ -36,17 +36,18 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (its GF(2)-linear first step is applied per lane and per tile), 14 for the
 # rest of mix13 (2 x [3 multiplies + add3], 2 x [64-bit shift + 2 XOR]), 1 add.
 REDUCE_VALU_OPS_PER_SOLUTION = 17
-# HBM traffic of one materialise launch of the headline step,
+# HBM traffic of one batch_enum_kernel<uint32_t, overlap> launch of the headline step,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch), each scaled by what the same counter reads for a plain 256 MiB
 # device copy (WRITE_SIZE 262144 KiB -> x1.0, FETCH_SIZE 131085 KiB -> x2.0).
 # Valid only for the kernel sources it was taken on (sha256 prefix below).
 ENUM_TRAFFIC = {
-    "src_sha256_16": "f71dd4f21246543f",
-    "fetch_kib_raw": 53.4, "fetch_scale": 2.0,
-    "write_kib_raw": 688809.0, "write_scale": 1.0,
+    "src_sha256_16": "d67352e4e85dcf19",
+    "fetch_kib_raw": 72.9, "fetch_scale": 2.0,
+    "write_kib_raw": 688825.6, "write_scale": 1.0,
 }
-ENUM_TRAFFIC_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/batch.hip")
+ENUM_TRAFFIC_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/batch.hip",
+                        "paper_2103_00693_amd/csrc/factor_wave.h")
 METRIC = "solutions enumerated/s (G/s) + % HBM/VALU roofline; batched instances/s, p99 latency"
 
 

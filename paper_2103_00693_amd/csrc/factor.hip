@@ -20,8 +20,8 @@ namespace hlf {
 namespace {
 
 // ---------------------------------------------------------------------------
-// A0: pack + validate.  One workgroup of 64*W threads; wave v packs rows
-// v, v + W, ... by ballot over 64 consecutive bytes, then checks A = A^T: for
+// A0: pack + validate.  One workgroup of 64*W threads; each wave packs groups
+// of rows by ballot over 64 consecutive bytes, then checks A = A^T: for
 // column c, the ballot of bit c over the 64 rows held by wave v is word v of
 // column c, which must equal word v of row c.
 // ---------------------------------------------------------------------------
@@ -38,15 +38,25 @@ __global__ __launch_bounds__(64 * WMAX) void pack_dense_kernel(const uint8_t *__
     if (tid == 0) bad = 0;
     __syncthreads();
 
+    // Wave v packs row groups v, v + nwaves, ... of G rows: lane l loads byte
+    // 64*w + l of the G rows at once (independent loads), then one ballot per
+    // row gives the packed word.
+    constexpr int G = 16;
     int mybad = 0;
-    for (int i = wave; i < n; i += nwaves) {
-        const uint8_t *src = A + (size_t)i * n;
+    for (int i0 = wave * G; i0 < n; i0 += nwaves * G) {
         for (int w = 0; w < W; ++w) {
             const int j = 64 * w + lane;
-            const uint8_t v = (j < n) ? src[j] : (uint8_t)0;
-            mybad |= (v > 1);
-            const uint64_t word = __ballot(v == 1);
-            if (lane == 0) lds[i * W + w] = word;
+            uint32_t v[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+                v[k] = (j < n && i0 + k < n) ? (uint32_t)A[(size_t)(i0 + k) * n + j] : 0u;
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                if (i0 + k >= n) break;
+                mybad |= (v[k] > 1u);
+                const uint64_t word = __ballot(v[k] == 1u);
+                if (lane == 0) lds[(i0 + k) * W + w] = word;
+            }
         }
     }
     __syncthreads();
@@ -110,11 +120,15 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
     const int wave = tid >> 6;
     const int nthr = blockDim.x;
 
+    // During validation and elimination `mat` is word-major (word w of row i
+    // at w*NP + i), so the 64 lanes of a wave store to consecutive addresses;
+    // afterwards it is reused row-major for the RREF and the kernel vectors.
+    constexpr int NP = 64 * WMAX;
     uint64_t row[WMAX];
 #pragma unroll
     for (int w = 0; w < WMAX; ++w) {
         row[w] = (tid < n && w < W) ? rows[tid * W + w] : 0ull;
-        if (tid < n && w < W) mat[tid * W + w] = row[w];
+        if (tid < n && w < W) mat[w * NP + tid] = row[w];
     }
     if (tid < WMAX) shiftw[tid] = 0;
     if (tid < 3) cand[tid] = INT_MAX;
@@ -136,7 +150,7 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
             const int c = 64 * cw + cb;
             if (c >= n) break;
             const uint64_t col = __ballot((row[cw] >> cb) & 1ull);
-            if (col != mat[c * W + wave]) bad = true;
+            if (col != mat[wave * NP + c]) bad = true;
         }
     }
     if (bad) flag_bad = 1;
@@ -150,7 +164,7 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
     }
 
     // Gauss-Jordan with one barrier per column.  `mat` holds every current row
-    // (row i at i*W, kept equal to thread i's registers).  Phase c: every
+    // (word-major, kept equal to thread i's registers).  Phase c: every
     // thread reads the pivot p of column c chosen before the barrier, XORs row
     // p (read from LDS) into its own row if it has bit c, stores its row back,
     // and offers itself as a candidate for column c+1 (atomicMin over
@@ -180,12 +194,11 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
             }
             if (tid == 0) piv[r] = c;
             if (((word >> cb) & 1ull) && tid != p) {
-                const uint64_t *prow_l = &mat[p * W];
 #pragma unroll
                 for (int w = 0; w < WMAX; ++w)
                     if (w < W) {
-                        row[w] ^= prow_l[w];
-                        mat[tid * W + w] = row[w];
+                        row[w] ^= mat[w * NP + p];
+                        mat[w * NP + tid] = row[w];
                     }
             }
             ++r;
