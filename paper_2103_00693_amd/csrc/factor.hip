@@ -20,11 +20,33 @@ namespace hlf {
 namespace {
 
 // ---------------------------------------------------------------------------
-// A0: pack + validate.  One workgroup of 64*W threads; each wave packs groups
-// of rows by ballot over 64 consecutive bytes, then checks A = A^T: for
-// column c, the ballot of bit c over the 64 rows held by wave v is word v of
-// column c, which must equal word v of row c.
+// A0: pack + validate.  One workgroup of 64*W threads packs A into bit rows in
+// LDS, then checks A = A^T: for column c, the ballot of bit c over the 64 rows
+// held by wave v is word v of column c, which must equal word v of row c.
+//
+// Packing: when n is a multiple of 16 and A is 16-byte aligned, each thread
+// loads 16 bytes (columns 16q..16q+15 of one row) per request, kPackU rows in
+// flight, and gathers them into 16 bits.  For a 32-bit word x holding four
+// 0/1 bytes b0..b3, (x * 0x10204080) >> 28 = b0 | b1<<1 | b2<<2 | b3<<3: the
+// partial product of b_k with 2^(28-7k) lands on bit 28+k, and every other
+// partial product lands on a distinct bit below 28 or above 31, so there are
+// no carries into bits 28..31.  Any other n falls back to byte loads (lane l
+// loads column 64w+l of G rows, one ballot per row).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t gather4(uint32_t x) { return (x * 0x10204080u) >> 28; }
+
+// Symmetry of one pair of 64x64 tiles: lane l holds x = word J of row 64I+l
+// and y = word I of row 64J+l.  Column b of tile (I, J) is the ballot of bit
+// b of x; it must equal y in lane b (row 64J+b restricted to columns
+// 64I..64I+63).  Returns true, wave-uniform, if some A[64I+l][64J+b] !=
+// A[64J+b][64I+l].  Needs all lanes active.
+__device__ __forceinline__ bool tile_pair_asym(uint64_t x, uint64_t y) {
+    uint64_t diff = 0;
+#pragma unroll 8
+    for (int b = 0; b < 64; ++b) diff |= __ballot((x >> b) & 1ull) ^ readlane64(y, b);
+    return diff != 0;
+}
+
 template <int WMAX>
 __global__ __launch_bounds__(64 * WMAX) void pack_dense_kernel(const uint8_t *__restrict__ A, int n,
                                                                int W, uint64_t *__restrict__ rows,
@@ -34,50 +56,83 @@ __global__ __launch_bounds__(64 * WMAX) void pack_dense_kernel(const uint8_t *__
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    const int nwaves = blockDim.x >> 6;
-    if (tid == 0) bad = 0;
-    __syncthreads();
-
-    // Wave v packs row groups v, v + nwaves, ... of G rows: lane l loads byte
-    // 64*w + l of the G rows at once (independent loads), then one ballot per
-    // row gives the packed word.
-    constexpr int G = 16;
+    const int nthr = blockDim.x;
+    const int nwaves = nthr >> 6;
     int mybad = 0;
-    for (int i0 = wave * G; i0 < n; i0 += nwaves * G) {
-        for (int w = 0; w < W; ++w) {
-            const int j = 64 * w + lane;
-            uint32_t v[G];
+
+    if ((n & 15) == 0 && ((uintptr_t)A & 15u) == 0) {
+        // Pieces of 16 bits; pieces past column n-1 of the last word stay 0.
+        for (int idx = tid; idx < n * W; idx += nthr) lds[idx] = 0;
+        if (tid == 0) bad = 0;
+        __syncthreads();
+        uint16_t *l16 = reinterpret_cast<uint16_t *>(lds);
+        const int cpr = n >> 4;             // 16-byte chunks per row, <= 4W
+        const int rpp = nthr / cpr;         // rows per pass, >= 16
+        const int ri = tid / cpr, q = tid - ri * cpr;
+        const u32x4 *A16 = reinterpret_cast<const u32x4 *>(A);
+        constexpr int kPackU = 16;
+        if (ri < rpp) {
+            for (int i0 = ri; i0 < n; i0 += kPackU * rpp) {
+                u32x4 v[kPackU];
 #pragma unroll
-            for (int k = 0; k < G; ++k)
-                v[k] = (j < n && i0 + k < n) ? (uint32_t)A[(size_t)(i0 + k) * n + j] : 0u;
+                for (int u = 0; u < kPackU; ++u) {
+                    const int i = i0 + u * rpp;
+                    v[u] = (i < n) ? __builtin_nontemporal_load(&A16[(size_t)i * cpr + q])
+                                   : u32x4{0u, 0u, 0u, 0u};
+                }
 #pragma unroll
-            for (int k = 0; k < G; ++k) {
-                if (i0 + k >= n) break;
-                mybad |= (v[k] > 1u);
-                const uint64_t word = __ballot(v[k] == 1u);
-                if (lane == 0) lds[(i0 + k) * W + w] = word;
+                for (int u = 0; u < kPackU; ++u) {
+                    const int i = i0 + u * rpp;
+                    if (i < n) {
+                        mybad |= ((v[u].x | v[u].y | v[u].z | v[u].w) & 0xFEFEFEFEu) != 0u;
+                        const uint32_t m = gather4(v[u].x) | (gather4(v[u].y) << 4) |
+                                           (gather4(v[u].z) << 8) | (gather4(v[u].w) << 12);
+                        l16[i * 4 * W + q] = (uint16_t)m;
+                    }
+                }
+            }
+        }
+    } else {
+        if (tid == 0) bad = 0;
+        __syncthreads();
+        // Wave v packs row groups v, v + nwaves, ... of G rows: lane l loads
+        // byte 64*w + l of the G rows at once (independent loads), then one
+        // ballot per row gives the packed word.
+        constexpr int G = 16;
+        for (int i0 = wave * G; i0 < n; i0 += nwaves * G) {
+            for (int w = 0; w < W; ++w) {
+                const int j = 64 * w + lane;
+                uint32_t v[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k)
+                    v[k] = (j < n && i0 + k < n) ? (uint32_t)A[(size_t)(i0 + k) * n + j] : 0u;
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    if (i0 + k >= n) break;
+                    mybad |= (v[k] > 1u);
+                    const uint64_t word = __ballot(v[k] == 1u);
+                    if (lane == 0) lds[(i0 + k) * W + w] = word;
+                }
             }
         }
     }
     __syncthreads();
 
-    const int i = tid;
-    uint64_t row[WMAX];
-#pragma unroll
-    for (int w = 0; w < WMAX; ++w) row[w] = (i < n && w < W) ? lds[i * W + w] : 0ull;
-#pragma unroll
-    for (int cw = 0; cw < WMAX; ++cw) {
-        if (cw >= W) break;
-        for (int cb = 0; cb < 64; ++cb) {
-            const int c = 64 * cw + cb;
-            if (c >= n) break;
-            const uint64_t col = __ballot((row[cw] >> cb) & 1ull);
-            if (col != lds[c * W + wave]) mybad = 1;
-        }
+    // Symmetry: tile pairs (I, J), I <= J < W, spread over the waves.
+    {
+        int pidx = 0;
+        for (int I = 0; I < W; ++I)
+            for (int J = I; J < W; ++J, ++pidx) {
+                if (pidx % nwaves != wave) continue;
+                const int ri = 64 * I + lane, rj = 64 * J + lane;
+                const uint64_t x = (ri < n) ? lds[ri * W + J] : 0ull;
+                const uint64_t y = (rj < n) ? lds[rj * W + I] : 0ull;
+                if (tile_pair_asym(x, y)) mybad = 1;
+            }
     }
     if (mybad) bad = 1;
     __syncthreads();
-    for (int idx = tid; idx < n * W; idx += blockDim.x) rows[idx] = lds[idx];
+    for (int idx = tid; idx < n * W; idx += nthr) rows[idx] = lds[idx];
     if (tid == 0) *status = bad ? HLF_ENOTSYM : HLF_OK;
 }
 
@@ -107,11 +162,18 @@ __device__ __forceinline__ int lower_bound_int(const int *a, int len, int key) {
 template <int WMAX>
 __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *__restrict__ rows,
                                                                 int n, int W, FactorOut out) {
-    __shared__ uint64_t mat[64 * WMAX * WMAX];
+    constexpr int NP = 64 * WMAX;
+    constexpr int kMatWords = 64 * WMAX * WMAX > 256 * WMAX ? 64 * WMAX * WMAX : 256 * WMAX;
+    __shared__ uint64_t mat[kMatWords];
+    __shared__ uint64_t prow[8 * WMAX];
     __shared__ int piv[64 * WMAX];
     __shared__ int freec[64 * WMAX];
     __shared__ int qacc[64 * WMAX];
-    __shared__ int cand[3];
+    __shared__ uint64_t planes[8 * 16];
+    __shared__ __align__(16) uint8_t sl8[1024];
+    __shared__ __align__(16) uint32_t blkstate[16];
+    __shared__ __align__(16) int pivinfo[8];
+    __shared__ int blk[2];
     __shared__ unsigned long long shiftw[WMAX];
     __shared__ int flag_bad, flag_internal;
 
@@ -120,18 +182,16 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
     const int wave = tid >> 6;
     const int nthr = blockDim.x;
 
-    // During validation and elimination `mat` is word-major (word w of row i
-    // at w*NP + i), so the 64 lanes of a wave store to consecutive addresses;
-    // afterwards it is reused row-major for the RREF and the kernel vectors.
-    constexpr int NP = 64 * WMAX;
+    // `mat` holds, in turn: A word-major (word w of row i at w*NP + i) for the
+    // symmetry check; the block tables of the elimination; the RREF rows and
+    // the kernel vectors, row-major.
     uint64_t row[WMAX];
 #pragma unroll
     for (int w = 0; w < WMAX; ++w) {
         row[w] = (tid < n && w < W) ? rows[tid * W + w] : 0ull;
-        if (tid < n && w < W) mat[w * NP + tid] = row[w];
+        mat[w * NP + tid] = row[w];
     }
     if (tid < WMAX) shiftw[tid] = 0;
-    if (tid < 3) cand[tid] = INT_MAX;
     if (tid == 0) {
         flag_bad = 0;
         flag_internal = 0;
@@ -143,15 +203,16 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
 #pragma unroll
     for (int w = 0; w < WMAX; ++w)
         if (w == W - 1 && (row[w] & ~lm)) bad = true;
-#pragma unroll
-    for (int cw = 0; cw < WMAX; ++cw) {
-        if (cw >= W) break;
-        for (int cb = 0; cb < 64; ++cb) {
-            const int c = 64 * cw + cb;
-            if (c >= n) break;
-            const uint64_t col = __ballot((row[cw] >> cb) & 1ull);
-            if (col != mat[wave * NP + c]) bad = true;
-        }
+    // Symmetry: tile pairs (I, J), I <= J < W, spread over the waves.
+    {
+        const int nwaves = nthr >> 6;
+        int pidx = 0;
+        for (int I = 0; I < W; ++I)
+            for (int J = I; J < W; ++J, ++pidx) {
+                if (pidx % nwaves != wave) continue;
+                if (tile_pair_asym(mat[J * NP + 64 * I + lane], mat[I * NP + 64 * J + lane]))
+                    bad = true;
+            }
     }
     if (bad) flag_bad = 1;
     __syncthreads();
@@ -163,61 +224,171 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
         return;
     }
 
-    // Gauss-Jordan with one barrier per column.  `mat` holds every current row
-    // (word-major, kept equal to thread i's registers).  Phase c: every
-    // thread reads the pivot p of column c chosen before the barrier, XORs row
-    // p (read from LDS) into its own row if it has bit c, stores its row back,
-    // and offers itself as a candidate for column c+1 (atomicMin over
-    // per-wave ballots).  Row p is not written in phase c, so all reads of it
-    // see one value; a candidate slot is reset two columns before its reuse,
-    // after every thread has read it.
-    int r = 0, nfree = 0, slot = 0;
+    // Gauss-Jordan in blocks of 8 columns (the blocking of Arlazarov,
+    // Dinic, Kronrod and Faradzev, the "Four Russians").  Within a block only
+    // the 8-bit slice s of every row takes part in the elimination: the
+    // pivot of column c is the lowest-index row that is not yet a pivot and
+    // has bit c of its current slice set, and every row keeps a tag tau (bit
+    // j set: the block's j-th pivot row, as it stood when the block began,
+    // has been added to it).  One column step maps the state (slice, tag) of
+    // every row other than that column's pivot by a linear map over GF(2)
+    // (add the pivot's state, plus bit j to the tag, if bit c is set), so
+    // the state of such a row is a linear function of its starting slice:
+    // the XOR of the states reached from the 8 unit slices.  Wave 0 keeps
+    // those 8 states in lanes 0-7 and the pivots' own states in lanes 8-15,
+    // and holds the slices of all rows as 8 bit-planes, 16 rows per lane.
+    // At step c the candidates are the unused rows whose slice has odd
+    // parity against w (bit k of w = bit c of unit state k): an XOR of at
+    // most 8 planes and a ballot.  The block ends with every row's tag; the
+    // current value of every row is then its start-of-block value plus the
+    // XOR of the pivot rows in its tag, so one lookup in the table T[tau]
+    // (2^m entries for m pivots) updates every row, pivot rows included.
+    int r = 0, nfree = 0;
     bool used = false;
     int myk = -1;
-    {
-        const uint64_t m = __ballot(tid < n && (row[0] & 1ull));
-        if (lane == 0 && m) atomicMin(&cand[0], wave * 64 + __builtin_ctzll(m));
-    }
-    __syncthreads();
-    for (int c = 0; c < n; ++c) {
-        const int p = cand[slot];
-        if (tid == 0) cand[slot == 0 ? 2 : slot - 1] = INT_MAX;
-        const int cw = c >> 6, cb = c & 63;
-        if (p != INT_MAX) {
-            uint64_t word = 0;
+    uint32_t unused16 = 0;  // wave 0: bit b of lane l <=> row 16l+b is not a pivot
+    if (wave == 0)
+        for (int b = 0; b < 16; ++b)
+            if (16 * lane + b < n) unused16 |= 1u << b;
+    for (int c0 = 0; c0 < n; c0 += 8) {
+        const int kb = (n - c0) < 8 ? (n - c0) : 8;
+        const int cw = c0 >> 6;
+        uint64_t word = 0;
 #pragma unroll
-            for (int w = 0; w < WMAX; ++w)
-                if (w == cw) word = row[w];
-            if (tid == p) {
-                used = true;
-                myk = r;
-            }
-            if (tid == 0) piv[r] = c;
-            if (((word >> cb) & 1ull) && tid != p) {
+        for (int w = 0; w < WMAX; ++w)
+            if (w == cw) word = row[w];
+        const uint32_t sl = (uint32_t)(word >> (c0 & 63)) & 0xFFu;
+        sl8[tid] = (uint8_t)sl;
 #pragma unroll
-                for (int w = 0; w < WMAX; ++w)
-                    if (w < W) {
-                        row[w] ^= mat[w * NP + p];
-                        mat[w * NP + tid] = row[w];
-                    }
-            }
-            ++r;
-        } else {
-            if (tid == 0) freec[nfree] = c;
-            ++nfree;
+        for (int k = 0; k < 8; ++k) {
+            const uint64_t pk = __ballot((sl >> k) & 1u);
+            if (lane == 0) planes[k * 16 + wave] = pk;
         }
-        const int nslot = (slot == 2) ? 0 : slot + 1;
-        if (c + 1 < n) {
-            const int c1 = c + 1;
-            uint64_t word1 = 0;
-#pragma unroll
-            for (int w = 0; w < WMAX; ++w)
-                if (w == (c1 >> 6)) word1 = row[w];
-            const uint64_t m = __ballot(tid < n && !used && ((word1 >> (c1 & 63)) & 1ull));
-            if (lane == 0 && m) atomicMin(&cand[nslot], wave * 64 + __builtin_ctzll(m));
-        }
-        slot = nslot;
         __syncthreads();
+
+        if (wave == 0) {
+            // cp[u]: bit b of lane l <=> bit u of the current slice of row
+            // 16l+b.  Lanes past the last row hold stale words; their rows are
+            // never candidates (unused16 is 0 there).
+            const int gw = lane >> 2, gs = 16 * (lane & 3);
+            uint32_t cp[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cp[k] = (uint32_t)(planes[k * 16 + gw] >> gs) & 0xFFFFu;
+            const u32x4 sq = *reinterpret_cast<const u32x4 *>(&sl8[16 * lane]);
+            // Lane k < 8: state of unit slice e_k (slice | tag << 8); lane 8+j:
+            // state of pivot j after its own step.
+            uint32_t st = (lane < 8) ? (1u << lane) : 0u;
+            int m = 0;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t >= kb) break;
+                const uint32_t cm = cp[t] & unused16;
+                const uint64_t bm = __ballot(cm != 0u);
+                if (bm == 0) {
+                    if (lane == 0) freec[nfree] = c0 + t;
+                    ++nfree;
+                    continue;
+                }
+                const int L = __builtin_ctzll(bm);
+                const int b = __builtin_ctz((uint32_t)__builtin_amdgcn_readlane((int)cm, L));
+                const uint32_t rbit = (lane == L) ? (1u << b) : 0u;
+                // Rows with bit t set, the pivot excluded, add the pivot's
+                // current slice; its bit t+1 is read directly so the next
+                // column's candidates do not wait for the unit states.
+                const uint32_t cpx = cp[t] & ~rbit;
+                unused16 &= ~rbit;
+                if (t + 1 < 8) {
+                    const uint32_t c1 =
+                        ((uint32_t)__builtin_amdgcn_readlane((int)cp[t + 1 < 8 ? t + 1 : 7], L) >> b) & 1u;
+                    if (c1) cp[t + 1 < 8 ? t + 1 : 7] ^= cpx;
+                }
+                const int q = b >> 2;
+                const uint32_t sw = q == 0 ? sq.x : q == 1 ? sq.y : q == 2 ? sq.z : sq.w;
+                const uint32_t sp =
+                    ((uint32_t)__builtin_amdgcn_readlane((int)sw, L) >> (8 * (b & 3))) & 0xFFu;
+                const uint32_t xr =
+                    xor_lanes0to7((lane < 8 && ((sp >> lane) & 1u)) ? st : 0u);
+#pragma unroll
+                for (int u = t + 2; u < 8; ++u)
+                    if ((xr >> u) & 1u) cp[u] ^= cpx;
+                const uint32_t upd = xr ^ (1u << (8 + m));
+                if (lane < 8 + m && ((st >> t) & 1u)) st ^= upd;
+                if (lane == 8 + m) st = xr;
+                if (lane == 0) {
+                    piv[r + m] = c0 + t;
+                    pivinfo[m] = 16 * L + b;
+                }
+                ++m;
+            }
+            if (lane < 16) blkstate[lane] = (st >> 8) & 0xFFu;
+            if (lane == 0) {
+                blk[0] = m;
+                blk[1] = nfree;
+            }
+        }
+        __syncthreads();
+        const int m = blk[0];
+        nfree = blk[1];
+        uint32_t tau = 0;
+        if (m > 0 && tid < n) {
+            const u32x4 bs0 = *reinterpret_cast<const u32x4 *>(&blkstate[0]);
+            const u32x4 bs1 = *reinterpret_cast<const u32x4 *>(&blkstate[4]);
+            const u32x4 bs2 = *reinterpret_cast<const u32x4 *>(&blkstate[8]);
+            const u32x4 bs3 = *reinterpret_cast<const u32x4 *>(&blkstate[12]);
+            const u32x4 pi0 = *reinterpret_cast<const u32x4 *>(&pivinfo[0]);
+            const u32x4 pi1 = *reinterpret_cast<const u32x4 *>(&pivinfo[4]);
+            const uint32_t us[8] = {bs0.x, bs0.y, bs0.z, bs0.w, bs1.x, bs1.y, bs1.z, bs1.w};
+            const uint32_t ps[8] = {bs2.x, bs2.y, bs2.z, bs2.w, bs3.x, bs3.y, bs3.z, bs3.w};
+            const uint32_t pr[8] = {pi0.x, pi0.y, pi0.z, pi0.w, pi1.x, pi1.y, pi1.z, pi1.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if ((sl >> k) & 1u) tau ^= us[k];
+            int j = -1;
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj)
+                if (jj < m && pr[jj] == (uint32_t)tid) j = jj;
+            if (j >= 0) {
+                used = true;
+                myk = r + j;
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj)
+                    if (jj == j) tau = ps[jj];
+#pragma unroll
+                for (int w = 0; w < WMAX; ++w) prow[j * WMAX + w] = row[w];
+            }
+        }
+        r += m;
+        if (m == 0) continue;
+        __syncthreads();
+        // T[e] word w at mat[w*256 + e]; thread (w, g) fills e = 4g .. 4g+3.
+        {
+            const int w = tid >> 6, g = tid & 63;
+            if (w < W && 4 * g < (1 << m)) {
+                uint64_t pr[8];
+#pragma unroll
+                for (int l = 0; l < 8; ++l) pr[l] = prow[l * WMAX + w];
+                uint64_t base = 0;
+#pragma unroll
+                for (int l = 2; l < 8; ++l)
+                    if (l < m && ((g >> (l - 2)) & 1)) base ^= pr[l];
+                const uint64_t p1 = (m > 1) ? pr[1] : 0ull;
+                uint64_t *te = &mat[w * 256 + 4 * g];
+                te[0] = base;
+                te[1] = base ^ pr[0];
+                te[2] = base ^ p1;
+                te[3] = base ^ pr[0] ^ p1;
+            }
+        }
+        __syncthreads();
+        if (tau) {
+            uint64_t tv[WMAX];
+#pragma unroll
+            for (int w = 0; w < WMAX; ++w) tv[w] = (w < W) ? mat[w * 256 + tau] : 0ull;
+#pragma unroll
+            for (int w = 0; w < WMAX; ++w) row[w] ^= tv[w];
+        }
+        // The next block's first write to planes, sl8, the block state or
+        // the table comes after at least one more barrier.
     }
     __syncthreads();
     if (used)
@@ -268,9 +439,17 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
     __syncthreads();
 
     for (int k = tid; k < n; k += nthr) out.pivots[k] = (k < r) ? piv[k] : -1;
-    for (int idx = tid; idx < r * W; idx += nthr) {
-        const int k = idx / W, w = idx - k * W;
-        out.basis[idx] = rows[piv[k] * W + w];
+    for (int idx0 = tid; idx0 < r * W; idx0 += 4 * nthr) {
+        uint64_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = idx0 + u * nthr;
+            const int k = idx / W, w = idx - k * W;
+            v[u] = (idx < r * W) ? rows[piv[k] * W + w] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (idx0 + u * nthr < r * W) out.basis[idx0 + u * nthr] = v[u];
     }
     if (tid < W) out.shift[tid] = shiftw[tid];
     if (tid == 0) {

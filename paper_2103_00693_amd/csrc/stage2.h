@@ -24,7 +24,6 @@
 
 namespace hlf {
 
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Status/range gate of every stage-2 kernel.  Returns false (and the caller
 // writes nothing) if the record is bad or [begin, begin+count) is not inside
