@@ -2,12 +2,15 @@
 // tasks (1)-(4)) on gfx950:
 //   * pack_dense_kernel: dense 0/1 matrix -> packed uint64 rows, with the
 //     symmetry / 0-1 validation of the problem statement (Section 1);
-//   * factor_wave_kernel: one wavefront per instance for n <= 192; every
-//     lane keeps its rows in VGPRs, pivots are found with a ballot and the
-//     pivot row is broadcast with readlane -- no barriers in the elimination;
+//   * factor_wave_kernel: one wavefront per instance (used for n <= 64; the
+//     batch path runs the same elimination for n <= 192); every lane keeps
+//     its rows in VGPRs, pivots are found with a ballot and the pivot row is
+//     broadcast with readlane -- no barriers in the elimination;
 //   * factor_workgroup_kernel: one workgroup per instance for n <= 1024, one
-//     row per thread (VGPRs, mirrored in LDS), pivot choice by an LDS
-//     atomicMin over per-wave ballots, one barrier per column.
+//     row per thread in VGPRs, Gauss-Jordan in blocks of 8 columns: the
+//     pivot search runs on bit-planes of the rows' 8-bit slices in one wave,
+//     then every row applies its block update with one lookup in a table of
+//     XOR combinations of the block's pivot rows (LDS).
 // Both variants produce the canonical record defined in hlf.h (the RREF is
 // unique, so the pivot rows chosen do not matter).
 #include "factor_wave.h"
@@ -174,6 +177,7 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
     __shared__ __align__(16) uint32_t blkstate[16];
     __shared__ __align__(16) int pivinfo[8];
     __shared__ int blk[2];
+    __shared__ uint32_t wmask;
     __shared__ unsigned long long shiftw[WMAX];
     __shared__ int flag_bad, flag_internal;
 
@@ -357,16 +361,28 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
                 for (int w = 0; w < WMAX; ++w) prow[j * WMAX + w] = row[w];
             }
         }
+        if (tid == 0) wmask = 0;
         r += m;
         if (m == 0) continue;
         __syncthreads();
         // T[e] word w at mat[w*256 + e]; thread (w, g) fills e = 4g .. 4g+3.
+        // Words that are zero in every pivot row (all words left of the
+        // block's word, since a row that is not yet a pivot is zero in every
+        // column already eliminated or found free) are skipped here and in
+        // the lookup; wmask records the others.
         {
             const int w = tid >> 6, g = tid & 63;
-            if (w < W && 4 * g < (1 << m)) {
-                uint64_t pr[8];
+            uint64_t pr[8];
+            uint64_t nz = 0;
+            if (w < W) {
 #pragma unroll
-                for (int l = 0; l < 8; ++l) pr[l] = prow[l * WMAX + w];
+                for (int l = 0; l < 8; ++l) {
+                    pr[l] = prow[l * WMAX + w];
+                    if (l < m) nz |= pr[l];
+                }
+                if (g == 0 && nz) atomicOr(&wmask, 1u << w);
+            }
+            if (w < W && nz && 4 * g < (1 << m)) {
                 uint64_t base = 0;
 #pragma unroll
                 for (int l = 2; l < 8; ++l)
@@ -380,10 +396,11 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
             }
         }
         __syncthreads();
+        const uint32_t wm = (uint32_t)__builtin_amdgcn_readfirstlane((int)wmask);
         if (tau) {
             uint64_t tv[WMAX];
 #pragma unroll
-            for (int w = 0; w < WMAX; ++w) tv[w] = (w < W) ? mat[w * 256 + tau] : 0ull;
+            for (int w = 0; w < WMAX; ++w) tv[w] = ((wm >> w) & 1u) ? mat[w * 256 + tau] : 0ull;
 #pragma unroll
             for (int w = 0; w < WMAX; ++w) row[w] ^= tv[w];
         }
@@ -495,11 +512,9 @@ hlf_status launch_pack(const uint8_t *A, int n, int W, uint64_t *rows, int32_t *
 
 hlf_status launch_factor(const uint64_t *rows, int n, int W, const FactorOut &out,
                          bool force_workgroup, hipStream_t stream) {
-    if (!force_workgroup) {
-        if (W == 1) return launch_wave_t<1>(rows, n, W, out, stream);
-        if (W == 2) return launch_wave_t<2>(rows, n, W, out, stream);
-        if (W == 3) return launch_wave_t<3>(rows, n, W, out, stream);
-    }
+    // One wave is faster up to n = 64; from two words on, the blocked
+    // workgroup elimination is.
+    if (!force_workgroup && W == 1) return launch_wave_t<1>(rows, n, W, out, stream);
     if (W <= 1) return launch_workgroup_t<1>(rows, n, W, out, stream);
     if (W <= 2) return launch_workgroup_t<2>(rows, n, W, out, stream);
     if (W <= 4) return launch_workgroup_t<4>(rows, n, W, out, stream);
