@@ -109,6 +109,15 @@ def random_symmetric(n: int, seed: int, density: float = 0.5) -> np.ndarray:
     return A.astype(np.uint8)
 
 
+def low_rank_symmetric(n: int, k: int, seed: int) -> np.ndarray:
+    """A symmetric 0/1 matrix of rank at most k: A = M^T M mod 2 with M a
+    uniform random k x n 0/1 matrix (a graph whose adjacency has a small
+    GF(2) rank, so all of its solutions can be enumerated at large n)."""
+    rng = np.random.default_rng(seed)
+    M = rng.integers(0, 2, size=(k, n)).astype(np.int64)
+    return ((M.T @ M) % 2).astype(np.uint8)
+
+
 def batch_instances(count: int = 4096, master_seed: int = 0):
     """The batched workload: grid side N ~ U{3..12}, p ~ U{0.3, 0.5, 1.0}.
 

@@ -396,6 +396,78 @@ def sample(F: dict, seed: int, num: int, coeffs=None) -> list[int]:
 
 
 # ----------------------------------------------------------------------------
+# Distribution statistics and membership (verification, Section 5: the ideal
+# output distribution as the input of a cross-entropy benchmark)
+# ----------------------------------------------------------------------------
+
+def pair_counts(F: dict):
+    """C[i][j] = number of solutions with z_{i+1} = z_{j+1} = 1, by plain
+    counting over every solution (direct definition, Gray order).  C[i][i] is
+    the per-qubit count of reduce mode.  Python ints (exact)."""
+    n, r = F["n"], F["rank"]
+    C = [[0] * n for _ in range(n)]
+    for z in enumerate_range(F, 0, 1 << r):
+        ones = [j for j in range(n) if (z >> j) & 1]
+        for i in ones:
+            for j in ones:
+                C[i][j] += 1
+    return C
+
+
+def pair_quarters(A) -> np.ndarray:
+    """4 * P(z_i = z_j = 1) for a uniform solution z, in closed form.
+
+    Writing z = l XOR sum_k c_k B_k with c uniform, coordinate i is l_i plus
+    the functional c -> <c, beta_i>, beta_i = (B_k[i])_k = row i of A at the
+    pivot columns.  Because the pivot columns are an information set of the
+    row space, beta_i = beta_j exactly when A_i = A_j and beta_i = 0 exactly
+    when A_i = 0.  Hence: a zero row gives z_i = 0 always (e_i is in Ker(A)
+    with q = 0); two equal nonzero rows give z_i = z_j always (e_i + e_j is
+    in Ker(A) with q = 4 A_ij = 0 mod 4), so the pair is 1 with probability
+    1/2; distinct nonzero rows give independent uniform bits, probability
+    1/4.  Pinned against pair_counts by brute force in the tests.
+    """
+    A = validate(A)
+    n = A.shape[0]
+    Q = np.zeros((n, n), dtype=np.int64)
+    for i in range(n):
+        for j in range(n):
+            if not A[i].any() or not A[j].any():
+                Q[i, j] = 0
+            elif np.array_equal(A[i], A[j]):
+                Q[i, j] = 2
+            else:
+                Q[i, j] = 1
+    return Q
+
+
+def is_solution(A, z: int, kernel=None) -> bool:
+    """The problem's definition (Section 1): q(x) = 2 z.x mod 4 for every x in
+    Ker(A).  q is linear on Ker(A) (values in {0, 2}), so checking a basis of
+    Ker(A) suffices; ``kernel`` may pass that basis (ints), else it is
+    computed.  The tests pin this against all of span(Ker) for tiny n."""
+    A = validate(A)
+    n = A.shape[0]
+    ks = kernel_basis(A) if kernel is None else kernel
+    for k in ks:
+        x = bits_to_array(k, n) if isinstance(k, int) else np.asarray(k)
+        zx = sum(((z >> j) & 1) * int(x[j]) for j in range(n))
+        if (q_form(A, x) - 2 * zx) % 4 != 0:
+            return False
+    return True
+
+
+def linear_xeb(n: int, r: int, members) -> float:
+    """Linear cross-entropy benchmark estimate 2^n * mean(p(z_s)) - 1 with
+    the ideal probabilities p(z) = 2^-r on the solution set and 0 elsewhere
+    (App. A): 2^(n-r) * (fraction of samples that are solutions) - 1."""
+    members = list(members)
+    if not members:
+        raise ValueError("no samples")
+    return (2.0 ** (n - r)) * (sum(1 for m in members if m) / len(members)) - 1.0
+
+
+# ----------------------------------------------------------------------------
 # The quantum circuit of Appendix A, as a dense state vector
 # ----------------------------------------------------------------------------
 

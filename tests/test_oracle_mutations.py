@@ -131,3 +131,45 @@ def test_shift_on_pivots_instead_of_free_columns_is_caught(monkeypatch):
         return l
     monkeypatch.setattr(O, "canonical_shift", shift_on_pivots)
     assert fails(pins_for_factor)
+
+
+import test_oracle_stats as ST
+
+
+def pins_for_stats():
+    for A in ST._instances():
+        ST.test_pair_quarters_closed_form_equals_counting(A)
+    for A in [a for a in ST._instances() if a.shape[0] <= 9]:
+        ST.test_is_solution_matches_brute_force(A)
+    ST.test_linear_xeb_exact_and_uniform_samples()
+
+
+def test_unmutated_stats_pins_pass():
+    pins_for_stats()
+
+
+def test_equal_rows_treated_as_independent_is_caught(monkeypatch):
+    orig = O.pair_quarters
+
+    def independent_always(A):
+        Q = orig(A)
+        n = Q.shape[0]
+        for i in range(n):
+            for j in range(n):
+                if i != j and Q[i, j] == 2:
+                    Q[i, j] = 1
+        return Q
+    monkeypatch.setattr(O, "pair_quarters", independent_always)
+    assert fails(pins_for_stats)
+
+
+def test_membership_without_the_quadratic_term_is_caught(monkeypatch):
+    def linear_only(A, z, kernel=None):
+        A = O.validate(A)
+        n = A.shape[0]
+        for k in O.kernel_basis(A):
+            if bin(k & z).count("1") % 2:
+                return False
+        return True
+    monkeypatch.setattr(O, "is_solution", linear_only)
+    assert fails(pins_for_stats)

@@ -362,3 +362,21 @@ def test_c_oracle_counter_order_equals_literal_circuit():
             assert got == O.enumerate_counter_order(A, F, begin, count)
         assert set(int(z[0]) for z in C.enumerate_counter_range(F, 0, min(total, 1 << 12))) <= \
             set(int(z[0]) for z in C.enumerate_range(F, 0, total))
+
+
+def test_c_oracle_counter_order_equals_literal_circuit_any_graph():
+    """Section 5: the same circuit, one ROU per edge of G(A) plus the Toffoli
+    layer, serves any symmetric A.  The C counter-order enumerator (basis
+    form) equals it on random graphs with self-loops and on low-rank graphs,
+    multi-word included."""
+    from hlf_inputs import low_rank_symmetric
+    cases = [random_symmetric(n, seed=60 + n, density=d) for n, d in [(6, 0.5), (9, 0.3), (12, 0.6)]]
+    cases += [low_rank_symmetric(70, 9, 1), low_rank_symmetric(130, 7, 2)]
+    for A in cases:
+        F = O.factor(A)
+        total = 1 << F["rank"]
+        for begin, count in [(0, min(total, 200)), (max(0, total - 33), min(total, 33))]:
+            got = C.enumerate_counter_range(F, begin, count)
+            want = O.enumerate_counter_order(A, F, begin, count)
+            W = F["words"]
+            assert [sum(int(zw) << (64 * w) for w, zw in enumerate(z)) for z in got] == want
