@@ -155,6 +155,104 @@ def steady_mode(hlf, torch, stream, dev):
             "solutions_per_s_G": round(count / s / 1e9, 1)}
 
 
+def _timed(torch, stream, fn, reps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    fn()
+    stream.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def general_mode(hlf, torch, stream, dev):
+    """Arbitrary symmetric A (Section 5): (a) a dense random graph with
+    self-loops at n = 1024 (density 0.5): stage 1 and 65536 uniform samples;
+    (b) a low-rank graph at n = 1024 (A = M^T M, M 24 x 1024): all 2^r
+    solutions as 16-word vectors, in counter order (the paper's circuit order)
+    and in Gray order."""
+    from hlf_inputs import low_rank_symmetric, random_symmetric
+
+    out = {}
+    A = torch.from_numpy(random_symmetric(1024, seed=1, density=0.5)).to(dev)
+    rows = torch.empty((1024, 16), dtype=torch.int64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    F = hlf.Factors(1024, device=dev)
+    hlf.pack_dense(A, rows, st, stream=stream)
+    hlf.factor(rows, 1024, F, stream=stream)
+    stream.synchronize()
+    F.check()
+    smp = torch.empty((65536, 16), dtype=torch.int64, device=dev)
+    out["dense"] = {
+        "workload": "random symmetric 0/1 matrix, n=1024, density 0.5 (self-loops included)",
+        "rank": int(F.rank.item()),
+        "pack_ms": round(_timed(torch, stream, lambda: hlf.pack_dense(A, rows, st, stream=stream), 5) * 1e3, 4),
+        "factor_ms": round(_timed(torch, stream, lambda: hlf.factor(rows, 1024, F, stream=stream), 5) * 1e3, 4),
+        "ms_per_65536_samples": round(_timed(torch, stream, lambda: hlf.sample(F, 3, 65536, out=smp, stream=stream), 5) * 1e3, 4),
+    }
+    del smp
+    A = torch.from_numpy(low_rank_symmetric(1024, 24, seed=2)).to(dev)
+    hlf.pack_dense(A, rows, st, stream=stream)
+    hlf.factor(rows, 1024, F, stream=stream)
+    stream.synchronize()
+    F.check()
+    r = int(F.rank.item())
+    count = 1 << r
+    buf = torch.empty((count, 16), dtype=torch.int64, device=dev)
+    bytes_ = count * 128
+    res = {"workload": "low-rank symmetric A = M^T M mod 2, M uniform 24 x 1024: all 2^r solutions as 16 uint64 words",
+           "rank": r, "bytes": bytes_, "kernel": "enum_general_kernel<16, uint64_t>"}
+    for order in ("counter", "gray"):
+        sec = _timed(torch, stream,
+                     lambda: hlf.enumerate_solutions(F, 0, count, 1024, out=buf, stream=stream, order=order), 3)
+        res[order] = {"ms": round(sec * 1e3, 3), "achieved_GBs": round(bytes_ / sec / 1e9, 1),
+                      "frac_of_8TBs": round(bytes_ / sec / 8e12, 4),
+                      "solutions_per_s_G": round(count / sec / 1e9, 3)}
+    F.check()
+    out["low_rank"] = res
+    del buf
+    return out
+
+
+def verify_mode(hlf, torch, stream, dev):
+    """Verification data at n = 1024 (N=32 grid, p=0.5): membership of 2^20
+    strings (ideal probabilities for a cross-entropy benchmark), the linear
+    XEB of exact samples and of uniform strings, and the pair statistics."""
+    from hlf_inputs import grid_instance
+
+    A = torch.from_numpy(grid_instance(32, p=0.5, seed=17)).to(dev)
+    rows, st = hlf.pack_dense(A, stream=stream)
+    F = hlf.factor(rows, 1024, stream=stream)
+    stream.synchronize()
+    F.check()
+    n, r = 1024, int(F.rank.item())
+    num = 1 << 20
+    z = hlf.sample(F, 11, num, stream=stream)
+    mem = torch.empty(num, dtype=torch.uint8, device=dev)
+    t_mem = _timed(torch, stream, lambda: hlf.membership(F, z, out=mem, stream=stream), 5)
+    xeb_exact = hlf.linear_xeb(n, r, mem)
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    u = torch.randint(-(1 << 62), 1 << 62, (num, 16), dtype=torch.int64, device=dev, generator=g)
+    hlf.membership(F, u, out=mem, stream=stream)
+    stream.synchronize()
+    uniform_members = int(mem.sum().item())
+    q = torch.empty((n, n), dtype=torch.uint8, device=dev)
+    t_pair = _timed(torch, stream, lambda: hlf.pair_stats(F, rows, out=q, stream=stream), 5)
+    hist = torch.bincount(q.flatten().to(torch.int64), minlength=3).cpu().tolist()
+    return {"workload": "N=32 grid (n=1024), p=0.5: membership of 2^20 strings, pair statistics",
+            "rank": r, "membership_strings_per_s": round(num / t_mem, 1),
+            "membership_ms_per_2^20": round(t_mem * 1e3, 4),
+            "kernel_vectors": n - r,
+            "xeb_exact_samples": xeb_exact, "xeb_exact_expected": 2.0 ** (n - r) - 1.0,
+            "uniform_strings_that_are_solutions": uniform_members,
+            "pair_stats_ms": round(t_pair * 1e3, 4),
+            "pair_quarters_histogram_0_1_2": hist[:3]}
+
+
 def batch_mode(hlf, torch, stream, dev):
     """4096 instances (N ~ U{3..12}, p ~ U{0.3, 0.5, 1.0}): factor every
     instance and reduce every instance with r <= 28.  Batched: the tuned
@@ -457,6 +555,8 @@ def main():
         modes["tiny"] = tiny_mode(hlf, torch, stream, dev)
         modes["steady"] = steady_mode(hlf, torch, stream, dev)
         modes["batch"] = batch_mode(hlf, torch, stream, dev)
+        modes["general"] = general_mode(hlf, torch, stream, dev)
+        modes["verify"] = verify_mode(hlf, torch, stream, dev)
         modes["serve"] = serve_mode(torch)
         result["modes"] = modes
 

@@ -94,6 +94,9 @@ typedef enum hlf_status {
 /* Flags of hlf_factor_ex. */
 #define HLF_FACTOR_WORKGROUP 1u /* force the workgroup (LDS) variant for any n   */
 
+/* Flags of hlf_enumerate_ex. */
+#define HLF_ORDER_COUNTER 1u    /* binary-counter order (Section 4) instead of Gray */
+
 /* Device-resident factor record (paper Section 2, tasks (1)-(4)).  The host
  * fills n and words and points the remaining members at caller-owned device
  * buffers of the stated sizes; hlf_factor writes them.                         */
@@ -156,6 +159,18 @@ hlf_status hlf_factor_ex(const uint64_t *rows_dev, const hlf_factors *f, uint32_
 hlf_status hlf_enumerate(const hlf_factors *f, uint64_t begin, uint64_t count,
                          int32_t word_bits, void *out_dev, hipStream_t stream);
 
+/* hlf_enumerate with flags.  HLF_ORDER_COUNTER: solution number i is
+ * z_i = l XOR (XOR over set bits k of i of B_k), the output of the paper's
+ * circuit fed by the binary counter of the FPGA design (Section 4); the
+ * circuit is defined for the graph of any symmetric A (Section 5), and this
+ * is its output for every A (the tile algebra runs on the prefix sums
+ * B_0 ^ ... ^ B_k, whose Gray-order walk is the counter order of B).
+ * Without flags: hlf_enumerate (Gray order).  Arguments, errors as there.
+ * Returns HLF_EINVAL for unknown flags.                                         */
+hlf_status hlf_enumerate_ex(const hlf_factors *f, uint64_t begin, uint64_t count,
+                            int32_t word_bits, uint32_t flags, void *out_dev,
+                            hipStream_t stream);
+
 /* Stage 2 as the paper's circuit, evaluated literally (Section 2, Eqs. (1)-(2),
  * Fig. 1(c)) in the binary-counter order of the FPGA design (Section 4):
  * for i in [begin, begin + count), R carries bit k of i at the pivot position
@@ -194,6 +209,32 @@ hlf_status hlf_enumerate_reduce(const hlf_factors *f, uint64_t begin, uint64_t c
  * Works for any r (no 62-bit limit).  num = 0 enqueues nothing.                 */
 hlf_status hlf_sample(const hlf_factors *f, uint64_t seed, uint64_t num,
                       const uint64_t *coeffs_dev, uint64_t *out_dev, hipStream_t stream);
+
+/* Verification data (Section 5: the ideal output distribution as the input
+ * of a cross-entropy benchmark of a device running the circuit).
+ *
+ * Pair statistics of a uniform solution z, exact for any r:
+ *   quarters_dev[i*n + j] = 4 * P(z_i = 1 and z_j = 1) (uint8, n*n entries);
+ * the diagonal holds 4 * P(z_i = 1).  Closed form: with A_i the rows of A,
+ * 0 if A_i = 0 or A_j = 0 (then z_i = 0 or z_j = 0 always), 2 if A_i = A_j
+ * is nonzero (then z_i = z_j always), else 1 (independent uniform bits).
+ *   rows_dev  the packed rows the record f was factored from (n x W words).
+ * Gated on f->status: nothing is written unless it is HLF_OK.
+ * Returns HLF_EINVAL for NULL pointers or a malformed record.                   */
+hlf_status hlf_pair_stats(const hlf_factors *f, const uint64_t *rows_dev, uint8_t *quarters_dev,
+                          hipStream_t stream);
+
+/* Membership: member_dev[s] = 1 if z_s = z_dev[s*W .. s*W+W-1] is a solution
+ * (the problem's definition, Section 1: q(x) = 2 z.x mod 4 for every x in
+ * Ker(A); on the kernel basis k_f this is <k_f, z> = l_f mod 2), else 0.
+ * The ideal probability of z_s is 2^-r * member_dev[s], and the linear
+ * cross-entropy estimate over S samples is 2^(n-r) * (sum of member) / S - 1.
+ *   f         record with a kernel buffer (f->kernel != NULL), filled by
+ *             hlf_factor.  num = 0 enqueues nothing.
+ * Gated on f->status: nothing is written unless it is HLF_OK.
+ * Returns HLF_EINVAL for NULL pointers, f->kernel == NULL or a malformed record. */
+hlf_status hlf_membership(const hlf_factors *f, const uint64_t *z_dev, uint64_t num,
+                          uint8_t *member_dev, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Batches: many instances of mixed n handled by one launch per stage (the

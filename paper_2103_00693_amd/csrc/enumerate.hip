@@ -23,17 +23,39 @@ __device__ __forceinline__ bool gate(const FactorIn &f, uint64_t begin, uint64_t
     return hlf::gate(f.status, f.rank, begin, count, r);
 }
 
+// Counter order (one word per basis vector): Bx[j] <- B_0 ^ ... ^ B_j for
+// j < r, by an inclusive prefix-XOR scan across the 64 lanes of wave 0.  The
+// Gray-order walk over these prefix sums visits l ^ XOR_{bit j of i} B_j at
+// index i, since g^-1 maps y to its prefix parities (bit j = XOR of y_k,
+// k >= j).  The caller synchronises the workgroup afterwards.
+__device__ __forceinline__ void prefix_xor_basis_w1(uint64_t *Bx, int r) {
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    uint64_t v = Bx[lane];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t t = __shfl_up(v, d);
+        if (lane >= d) v ^= t;
+    }
+    if (lane < r) Bx[lane] = v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kTileThreads) void enum_tile_kernel(FactorIn f, uint64_t begin,
                                                                  uint64_t count,
                                                                  T *__restrict__ out,
-                                                                 uint64_t tiles_per_block) {
+                                                                 uint64_t tiles_per_block,
+                                                                 int counter) {
     constexpr int S = tile_shift<T>();
     __shared__ uint64_t Bx[64];
     int r;
     if (!gate(f, begin, count, r)) return;
     load_basis_padded<1>(f.basis, r, Bx, threadIdx.x, blockDim.x);
     __syncthreads();
+    if (counter) {
+        prefix_xor_basis_w1(Bx, r);
+        __syncthreads();
+    }
     const uint64_t end = begin + count;
     const uint64_t ntiles = ((end - 1) >> S) - (begin >> S) + 1;
     const uint64_t t0 = (uint64_t)blockIdx.x * tiles_per_block;
@@ -56,9 +78,10 @@ struct GenTables {
     uint64_t l[WMAX];
 };
 
-// Build tables from E_j = B_j ^ B_{j-1}; returns the number of digits in use.
+// Build tables from E_j = B_j ^ B_{j-1} (Gray order) or E_j = B_j (counter
+// order); returns the number of digits in use.
 template <int WMAX>
-__device__ int build_tables(const FactorIn &f, int r, int W, GenTables<WMAX> &g) {
+__device__ int build_tables(const FactorIn &f, int r, int W, bool counter, GenTables<WMAX> &g) {
     using G = GenTables<WMAX>;
     const int ndig = (r + G::kDigitBits - 1) / G::kDigitBits;
     for (int idx = threadIdx.x; idx < ndig * G::kEntries; idx += blockDim.x) {
@@ -69,7 +92,7 @@ __device__ int build_tables(const FactorIn &f, int r, int W, GenTables<WMAX> &g)
                 const int j = m * G::kDigitBits + q;
                 if (((v >> q) & 1) && j < r) {
                     acc ^= f.basis[(size_t)j * W + w];
-                    if (j > 0) acc ^= f.basis[(size_t)(j - 1) * W + w];
+                    if (j > 0 && !counter) acc ^= f.basis[(size_t)(j - 1) * W + w];
                 }
             }
             g.tab[idx * WMAX + w] = acc;
@@ -81,32 +104,40 @@ __device__ int build_tables(const FactorIn &f, int r, int W, GenTables<WMAX> &g)
 
 template <int WMAX, typename T>
 __global__ __launch_bounds__(256) void enum_general_kernel(FactorIn f, uint64_t begin,
-                                                           uint64_t count, T *__restrict__ out) {
+                                                           uint64_t count, T *__restrict__ out,
+                                                           int counter) {
     using G = GenTables<WMAX>;
     __shared__ G g;
     int r;
     if (!gate(f, begin, count, r)) return;
     const int W = f.words;
-    const int ndig = build_tables<WMAX>(f, r, W, g);
+    const int ndig = build_tables<WMAX>(f, r, W, counter != 0, g);
     __syncthreads();
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += stride) {
-        const uint64_t i = begin + j;
-        uint64_t z[WMAX];
-#pragma unroll
-        for (int w = 0; w < WMAX; ++w) z[w] = (w < W) ? g.l[w] : 0ull;
-        for (int m = 0; m < ndig; ++m) {
-            const int d = (int)((i >> (m * G::kDigitBits)) & (G::kEntries - 1));
-            const uint64_t *e = &g.tab[(m * G::kEntries + d) * WMAX];
-#pragma unroll
-            for (int w = 0; w < WMAX; ++w) z[w] ^= e[w];
+    if constexpr (WMAX == 1) {
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += stride) {
+            const uint64_t i = begin + j;
+            uint64_t z = g.l[0];
+            for (int m = 0; m < ndig; ++m) {
+                const int d = (int)((i >> (m * G::kDigitBits)) & (G::kEntries - 1));
+                z ^= g.tab[m * G::kEntries + d];
+            }
+            out[j] = (T)z;
         }
-        if constexpr (WMAX == 1) {
-            out[j] = (T)z[0];
-        } else {
-#pragma unroll
-            for (int w = 0; w < WMAX; ++w)
-                if (w < W) out[j * W + w] = z[w];
+    } else {
+        // WMAX lanes per solution, lane w computes and stores word w: the
+        // active lanes of a wave store one contiguous run of words.
+        const int w = (int)(threadIdx.x & (WMAX - 1));
+        const uint64_t stride = ((uint64_t)gridDim.x * blockDim.x) / WMAX;
+        for (uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WMAX; j < count;
+             j += stride) {
+            const uint64_t i = begin + j;
+            uint64_t z = (w < W) ? g.l[w] : 0ull;
+            for (int m = 0; m < ndig; ++m) {
+                const int d = (int)((i >> (m * G::kDigitBits)) & (G::kEntries - 1));
+                z ^= g.tab[(m * G::kEntries + d) * WMAX + w];
+            }
+            if (w < W) out[j * W + w] = z;
         }
     }
 }
@@ -294,7 +325,7 @@ __global__ __launch_bounds__(256) void reduce_general_kernel(FactorIn f, uint64_
     if (!gate(f, begin, count, r)) return;
     const int W = f.words;
     const int n = f.n;
-    const int ndig = build_tables<WMAX>(f, r, W, g);
+    const int ndig = build_tables<WMAX>(f, r, W, false, g);
     for (int j = threadIdx.x; j < 64 * WMAX; j += blockDim.x) part[j] = 0;
     __syncthreads();
     const int lane = lane_id();
@@ -373,7 +404,7 @@ uint64_t tiles_per_block_for(uint64_t ntiles, uint64_t max_blocks, uint64_t *blo
 }
 
 template <typename T>
-hlf_status launch_tile(const FactorIn &f, uint64_t begin, uint64_t count, T *out,
+hlf_status launch_tile(const FactorIn &f, uint64_t begin, uint64_t count, T *out, int counter,
                        hipStream_t stream) {
     constexpr int S = tile_shift<T>();
     const uint64_t end = begin + count;  // host: may wrap only for invalid ranges
@@ -387,19 +418,20 @@ hlf_status launch_tile(const FactorIn &f, uint64_t begin, uint64_t count, T *out
     const uint64_t tpb =
         tiles_per_block_for(ntiles, (uint64_t)device_cu_count() * kTileBlocksPerCU, &blocks);
     hipLaunchKernelGGL(enum_tile_kernel<T>, dim3((unsigned)blocks), dim3(kTileThreads), 0, stream,
-                       f, begin, count, out, tpb);
+                       f, begin, count, out, tpb, counter);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
 }
 
 template <int WMAX, typename T>
-hlf_status launch_general(const FactorIn &f, uint64_t begin, uint64_t count, T *out,
+hlf_status launch_general(const FactorIn &f, uint64_t begin, uint64_t count, T *out, int counter,
                           hipStream_t stream) {
-    uint64_t blocks = (count + 255) / 256;
+    const uint64_t per_block = 256 / WMAX;  // solutions per workgroup pass
+    uint64_t blocks = (count + per_block - 1) / per_block;
     const uint64_t cap = (uint64_t)device_cu_count() * 8;
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL((enum_general_kernel<WMAX, T>), dim3((unsigned)blocks), dim3(256), 0,
-                       stream, f, begin, count, out);
+                       stream, f, begin, count, out, counter);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
 }
 
@@ -434,29 +466,30 @@ hlf_status launch_reduce_wave(const FactorIn &f, uint64_t begin, uint64_t count,
 }  // namespace
 
 hlf_status launch_enumerate(const FactorIn &f, uint64_t begin, uint64_t count, int word_bits,
-                            void *out, hipStream_t stream) {
+                            bool counter_order, void *out, hipStream_t stream) {
     const int W = f.words;
+    const int c = counter_order ? 1 : 0;
     const bool aligned16 = ((uintptr_t)out & 15u) == 0;
     if (W == 1 && word_bits <= 64) {
         if (word_bits == 16) {
             if (aligned16 && begin % Vec<uint16_t>::V == 0)
-                return launch_tile<uint16_t>(f, begin, count, (uint16_t *)out, stream);
-            return launch_general<1, uint16_t>(f, begin, count, (uint16_t *)out, stream);
+                return launch_tile<uint16_t>(f, begin, count, (uint16_t *)out, c, stream);
+            return launch_general<1, uint16_t>(f, begin, count, (uint16_t *)out, c, stream);
         }
         if (word_bits == 32) {
             if (aligned16 && begin % Vec<uint32_t>::V == 0)
-                return launch_tile<uint32_t>(f, begin, count, (uint32_t *)out, stream);
-            return launch_general<1, uint32_t>(f, begin, count, (uint32_t *)out, stream);
+                return launch_tile<uint32_t>(f, begin, count, (uint32_t *)out, c, stream);
+            return launch_general<1, uint32_t>(f, begin, count, (uint32_t *)out, c, stream);
         }
         if (aligned16 && begin % Vec<uint64_t>::V == 0)
-            return launch_tile<uint64_t>(f, begin, count, (uint64_t *)out, stream);
-        return launch_general<1, uint64_t>(f, begin, count, (uint64_t *)out, stream);
+            return launch_tile<uint64_t>(f, begin, count, (uint64_t *)out, c, stream);
+        return launch_general<1, uint64_t>(f, begin, count, (uint64_t *)out, c, stream);
     }
     uint64_t *o = (uint64_t *)out;
-    if (W <= 2) return launch_general<2, uint64_t>(f, begin, count, o, stream);
-    if (W <= 4) return launch_general<4, uint64_t>(f, begin, count, o, stream);
-    if (W <= 8) return launch_general<8, uint64_t>(f, begin, count, o, stream);
-    return launch_general<16, uint64_t>(f, begin, count, o, stream);
+    if (W <= 2) return launch_general<2, uint64_t>(f, begin, count, o, c, stream);
+    if (W <= 4) return launch_general<4, uint64_t>(f, begin, count, o, c, stream);
+    if (W <= 8) return launch_general<8, uint64_t>(f, begin, count, o, c, stream);
+    return launch_general<16, uint64_t>(f, begin, count, o, c, stream);
 }
 
 hlf_status launch_circuit(const FactorIn &f, const int32_t *pivots, const uint64_t *rows, int N,

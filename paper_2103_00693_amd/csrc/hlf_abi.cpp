@@ -98,7 +98,13 @@ hlf_status hlf_factor(const uint64_t *rows_dev, const hlf_factors *f, hipStream_
 
 hlf_status hlf_enumerate(const hlf_factors *f, uint64_t begin, uint64_t count, int32_t word_bits,
                          void *out_dev, hipStream_t stream) {
+    return hlf_enumerate_ex(f, begin, count, word_bits, 0u, out_dev, stream);
+}
+
+hlf_status hlf_enumerate_ex(const hlf_factors *f, uint64_t begin, uint64_t count,
+                            int32_t word_bits, uint32_t flags, void *out_dev, hipStream_t stream) {
     if (!record_ok(f)) return HLF_EINVAL;
+    if (flags & ~HLF_ORDER_COUNTER) return HLF_EINVAL;
     const int W = f->words;
     const bool narrow = (word_bits == 16 || word_bits == 32 || word_bits == 64) &&
                         f->n <= word_bits;
@@ -106,7 +112,8 @@ hlf_status hlf_enumerate(const hlf_factors *f, uint64_t begin, uint64_t count, i
     if (!narrow && !wide) return HLF_EINVAL;
     if (count == 0) return HLF_OK;
     if (!out_dev) return HLF_EINVAL;
-    return hlf::launch_enumerate(view(f), begin, count, word_bits, out_dev, stream);
+    return hlf::launch_enumerate(view(f), begin, count, word_bits, (flags & HLF_ORDER_COUNTER) != 0,
+                                 out_dev, stream);
 }
 
 hlf_status hlf_enumerate_circuit(const hlf_factors *f, const uint64_t *rows_dev, int32_t grid_N,
@@ -138,6 +145,20 @@ hlf_status hlf_sample(const hlf_factors *f, uint64_t seed, uint64_t num,
     if (num == 0) return HLF_OK;
     if (!out_dev) return HLF_EINVAL;
     return hlf::launch_sample(view(f), seed, num, coeffs_dev, out_dev, stream);
+}
+
+hlf_status hlf_pair_stats(const hlf_factors *f, const uint64_t *rows_dev, uint8_t *quarters_dev,
+                          hipStream_t stream) {
+    if (!record_ok(f) || !rows_dev || !quarters_dev) return HLF_EINVAL;
+    return hlf::launch_pair_stats(view(f), rows_dev, quarters_dev, stream);
+}
+
+hlf_status hlf_membership(const hlf_factors *f, const uint64_t *z_dev, uint64_t num,
+                          uint8_t *member_dev, hipStream_t stream) {
+    if (!record_ok(f) || !f->kernel) return HLF_EINVAL;
+    if (num == 0) return HLF_OK;
+    if (!z_dev || !member_dev) return HLF_EINVAL;
+    return hlf::launch_membership(view(f), f->kernel, z_dev, num, member_dev, stream);
 }
 
 }  // extern "C"

@@ -35,7 +35,16 @@ hlf_status launch_pack(const uint8_t *A, int n, int W, uint64_t *rows, int32_t *
 hlf_status launch_factor(const uint64_t *rows, int n, int W, const FactorOut &out,
                          bool force_workgroup, hipStream_t stream);
 hlf_status launch_enumerate(const FactorIn &f, uint64_t begin, uint64_t count, int word_bits,
-                            void *out, hipStream_t stream);
+                            bool counter_order, void *out, hipStream_t stream);
+// Gray order.
+inline hlf_status launch_enumerate(const FactorIn &f, uint64_t begin, uint64_t count,
+                                   int word_bits, void *out, hipStream_t stream) {
+    return launch_enumerate(f, begin, count, word_bits, false, out, stream);
+}
+hlf_status launch_pair_stats(const FactorIn &f, const uint64_t *rows, uint8_t *quarters,
+                             hipStream_t stream);
+hlf_status launch_membership(const FactorIn &f, const uint64_t *kernel, const uint64_t *z,
+                             uint64_t num, uint8_t *member, hipStream_t stream);
 hlf_status launch_circuit(const FactorIn &f, const int32_t *pivots, const uint64_t *rows, int N,
                           uint64_t begin, uint64_t count, int word_bits, void *out,
                           hipStream_t stream);

@@ -28,13 +28,14 @@ HLF_ECANCELLED = -6
 HLF_EINTERNAL = -7
 HLF_MAX_N = 1024
 HLF_MAX_ENUM_RANK = 62
+HLF_ORDER_COUNTER = 1
 HLF_ACCUMULATE = 1
 HLF_FACTOR_WORKGROUP = 1
 
 EXPORTED = (
     "hlf_version", "hlf_status_string", "hlf_words_for", "hlf_pack_dense", "hlf_factor",
-    "hlf_factor_ex", "hlf_enumerate", "hlf_enumerate_circuit", "hlf_enumerate_reduce",
-    "hlf_sample",
+    "hlf_factor_ex", "hlf_enumerate", "hlf_enumerate_ex", "hlf_enumerate_circuit",
+    "hlf_enumerate_reduce", "hlf_sample", "hlf_pair_stats", "hlf_membership",
     "hlf_batch_create", "hlf_batch_destroy", "hlf_batch_get_layout", "hlf_batch_factor_dense",
     "hlf_batch_enumerate", "hlf_batch_enumerate_overlap", "hlf_batch_solve", "hlf_batch_reduce", "hlf_batch_tune", "hlf_batch_graph_capture",
     "hlf_batch_graph_launch",
@@ -87,6 +88,12 @@ def lib():
         L.hlf_factor_ex.argtypes = [vp, fp, u32, vp]
         L.hlf_enumerate.restype = i32
         L.hlf_enumerate.argtypes = [fp, u64, u64, i32, vp, vp]
+        L.hlf_enumerate_ex.restype = i32
+        L.hlf_enumerate_ex.argtypes = [fp, u64, u64, i32, u32, vp, vp]
+        L.hlf_pair_stats.restype = i32
+        L.hlf_pair_stats.argtypes = [fp, vp, vp, vp]
+        L.hlf_membership.restype = i32
+        L.hlf_membership.argtypes = [fp, vp, u64, vp, vp]
         L.hlf_enumerate_circuit.restype = i32
         L.hlf_enumerate_circuit.argtypes = [fp, vp, i32, u64, u64, i32, vp, vp]
         L.hlf_enumerate_reduce.restype = i32
@@ -211,15 +218,24 @@ _DTYPES = {16: torch.int16, 32: torch.int32, 64: torch.int64}
 
 
 def enumerate_solutions(F: Factors, begin: int, count: int, word_bits: int,
-                        out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """E1: hlf_enumerate into ``out`` (allocated when None)."""
+                        out: torch.Tensor | None = None, stream=None,
+                        order: str = "gray") -> torch.Tensor:
+    """E1: hlf_enumerate (order "gray") or hlf_enumerate_ex with
+    HLF_ORDER_COUNTER (order "counter") into ``out`` (allocated when None)."""
+    if order not in ("gray", "counter"):
+        raise HlfError(HLF_EINVAL, f"order {order!r}")
     if out is None:
         if word_bits in _DTYPES and F.n <= word_bits:
             out = torch.empty(count, dtype=_DTYPES[word_bits], device=F.device)
         else:
             out = torch.empty((count, word_bits // 64), dtype=torch.int64, device=F.device)
-    _check(lib().hlf_enumerate(F.c, begin, count, word_bits, _ptr(out) if count else None,
-                               _stream(stream)), "hlf_enumerate")
+    if order == "gray":
+        _check(lib().hlf_enumerate(F.c, begin, count, word_bits, _ptr(out) if count else None,
+                                   _stream(stream)), "hlf_enumerate")
+    else:
+        _check(lib().hlf_enumerate_ex(F.c, begin, count, word_bits, HLF_ORDER_COUNTER,
+                                      _ptr(out) if count else None, _stream(stream)),
+               "hlf_enumerate_ex")
     return out
 
 
@@ -260,6 +276,35 @@ def sample(F: Factors, seed: int, num: int, coeffs: torch.Tensor | None = None,
     _check(lib().hlf_sample(F.c, seed & ((1 << 64) - 1), num, _ptr(coeffs),
                             _ptr(out) if num else None, _stream(stream)), "hlf_sample")
     return out
+
+
+def pair_stats(F: Factors, rows: torch.Tensor, out: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+    """hlf_pair_stats -> uint8 (n, n): 4 * P(z_i = 1 and z_j = 1)."""
+    if out is None:
+        out = torch.empty((F.n, F.n), dtype=torch.uint8, device=F.device)
+    _check(lib().hlf_pair_stats(F.c, _ptr(rows), _ptr(out), _stream(stream)), "hlf_pair_stats")
+    return out
+
+
+def membership(F: Factors, z: torch.Tensor, out: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+    """hlf_membership -> uint8 (num,): 1 where z[s] (int64 (num, W)) is a solution."""
+    num = z.shape[0]
+    if out is None:
+        out = torch.empty(num, dtype=torch.uint8, device=F.device)
+    _check(lib().hlf_membership(F.c, _ptr(z) if num else None, num, _ptr(out) if num else None,
+                                _stream(stream)), "hlf_membership")
+    return out
+
+
+def linear_xeb(n: int, r: int, member: torch.Tensor) -> float:
+    """Linear cross-entropy estimate 2^(n-r) * mean(member) - 1 from membership
+    flags (ideal probability 2^-r on the solution set, 0 elsewhere)."""
+    num = int(member.numel())
+    if num == 0:
+        raise HlfError(HLF_EINVAL, "no samples")
+    return (2.0 ** (n - r)) * (int(member.sum().item()) / num) - 1.0
 
 
 # ---------------------------------------------------------------------------

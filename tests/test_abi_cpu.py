@@ -108,3 +108,26 @@ def test_batch_host_validation():
     assert L.hlf_batch_destroy(None) == hlf.HLF_OK
     assert L.hlf_batch_reduce(None, ctypes.c_void_p(8), 10, None, None) == hlf.HLF_EINVAL
     assert L.hlf_batch_graph_launch(None, None) == hlf.HLF_EINVAL
+
+
+def test_host_detected_errors_of_order_and_verification_calls():
+    L = hlf.lib()
+    f20 = _rec(20)
+    p = ctypes.c_void_p(16)
+    # unknown flag bits and the word_bits rule of hlf_enumerate
+    assert L.hlf_enumerate_ex(ctypes.byref(f20), 0, 4, 32, 2, p, None) == hlf.HLF_EINVAL
+    assert L.hlf_enumerate_ex(ctypes.byref(f20), 0, 4, 16, hlf.HLF_ORDER_COUNTER, p, None) == hlf.HLF_EINVAL
+    assert L.hlf_enumerate_ex(ctypes.byref(f20), 0, 4, 32, hlf.HLF_ORDER_COUNTER, None, None) == hlf.HLF_EINVAL
+    # count = 0 enqueues nothing
+    assert L.hlf_enumerate_ex(ctypes.byref(f20), 0, 0, 32, hlf.HLF_ORDER_COUNTER, None, None) == hlf.HLF_OK
+    assert L.hlf_pair_stats(ctypes.byref(f20), None, p, None) == hlf.HLF_EINVAL
+    assert L.hlf_pair_stats(ctypes.byref(f20), p, None, None) == hlf.HLF_EINVAL
+    bad = _rec(20, "status")
+    assert L.hlf_pair_stats(ctypes.byref(bad), p, p, None) == hlf.HLF_EINVAL
+    # membership needs the kernel buffer of the record
+    assert L.hlf_membership(ctypes.byref(f20), p, 3, p, None) == hlf.HLF_EINVAL
+    with_kernel = _rec(20)
+    with_kernel.kernel = 8
+    assert L.hlf_membership(ctypes.byref(with_kernel), None, 3, p, None) == hlf.HLF_EINVAL
+    assert L.hlf_membership(ctypes.byref(with_kernel), p, 3, None, None) == hlf.HLF_EINVAL
+    assert L.hlf_membership(ctypes.byref(with_kernel), None, 0, None, None) == hlf.HLF_OK
