@@ -204,7 +204,7 @@ def general_mode(hlf, torch, stream, dev):
     buf = torch.empty((count, 16), dtype=torch.int64, device=dev)
     bytes_ = count * 128
     res = {"workload": "low-rank symmetric A = M^T M mod 2, M uniform 24 x 1024: all 2^r solutions as 16 uint64 words",
-           "rank": r, "bytes": bytes_, "kernel": "enum_general_kernel<16, uint64_t>"}
+           "rank": r, "bytes": bytes_, "kernel": "enum_wide_tile_kernel<16>"}
     for order in ("counter", "gray"):
         sec = _timed(torch, stream,
                      lambda: hlf.enumerate_solutions(F, 0, count, 1024, out=buf, stream=stream, order=order), 3)

@@ -65,6 +65,84 @@ __global__ __launch_bounds__(kTileThreads) void enum_tile_kernel(FactorIn f, uin
 }
 
 // ---------------------------------------------------------------------------
+// Materialise, W > 1 words per solution: the tile algebra of the one-word
+// kernel with one lane per word.  A tile is 1024 consecutive indices; thread
+// (slot, w) = (tid / WMAX, tid % WMAX) holds word w of the per-lane constants
+// l ^ F(slot + P*u), u < WMAX, P = 1024 / WMAX, and word w of the tile constant
+// F(T << 10); every output word is one XOR and one 8-byte store, and the
+// active lanes of a wave store one contiguous run of words.
+// ---------------------------------------------------------------------------
+template <int WMAX>
+__global__ __launch_bounds__(kTileThreads) void enum_wide_tile_kernel(FactorIn f, uint64_t begin,
+                                                                      uint64_t count,
+                                                                      uint64_t *__restrict__ out,
+                                                                      uint64_t tiles_per_block,
+                                                                      int counter) {
+    constexpr int P = kTileThreads / WMAX;  // solutions per row of the tile
+    constexpr int U = WMAX;                 // rows per tile
+    constexpr int S = kLogTileThreads;      // log2(P * U)
+    constexpr int LOGP = S - (WMAX == 2 ? 1 : WMAX == 4 ? 2 : WMAX == 8 ? 3 : 4);
+    __shared__ uint64_t Bx[64 * WMAX];
+    int r;
+    if (!gate(f, begin, count, r)) return;
+    const int W = f.words;
+    for (int idx = threadIdx.x; idx < 64 * WMAX; idx += blockDim.x) {
+        const int j = idx / WMAX, w = idx - j * WMAX;
+        Bx[idx] = (j < r && w < W) ? f.basis[(size_t)j * W + w] : 0ull;
+    }
+    __syncthreads();
+    if (counter) {
+        // Prefix sums B_0 ^ ... ^ B_j (j < r) of word w, by wave w.
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        if (wv < W) {
+            uint64_t v = Bx[lane * WMAX + wv];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint64_t t = __shfl_up(v, d);
+                if (lane >= d) v ^= t;
+            }
+            if (lane < r) Bx[lane * WMAX + wv] = v;
+        }
+        __syncthreads();
+    }
+    const uint64_t end = begin + count;
+    const uint64_t ntiles = ((end - 1) >> S) - (begin >> S) + 1;
+    const uint64_t t0 = (uint64_t)blockIdx.x * tiles_per_block;
+    if (t0 >= ntiles) return;
+    const uint64_t t1 = (t0 + tiles_per_block < ntiles) ? t0 + tiles_per_block : ntiles;
+
+    const int w = (int)(threadIdx.x & (WMAX - 1));
+    const int slot = (int)(threadIdx.x / WMAX);
+    // lo[u] = l ^ F(slot + P*u): F(P * 2^k) = E_{LOGP + k}, built along u.
+    uint64_t lo[U];
+    lo[0] = ((w < W) ? f.shift[w] : 0ull) ^ F_low<WMAX>(Bx, (uint64_t)slot, LOGP, w);
+#pragma unroll
+    for (int u = 1; u < U; ++u)
+        lo[u] = lo[u & (u - 1)] ^ E_at<WMAX>(Bx, LOGP + __builtin_ctz(u), w);
+    uint64_t Tt = (begin >> S) + t0;
+    uint64_t hi = F_tile<WMAX>(Bx, Tt, S, w);
+    const bool act = w < W;
+    for (uint64_t t = t0; t < t1; ++t, ++Tt) {
+        const uint64_t base = Tt << S;
+        if (base >= begin && base + (1u << S) <= end) {
+            if (act) {
+                uint64_t *o = out + (base - begin + (uint64_t)slot) * W + w;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    __builtin_nontemporal_store(lo[u] ^ hi, o + (uint64_t)u * P * W);
+            }
+        } else if (act) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t i = base + (uint64_t)slot + (uint64_t)u * P;
+                if (i >= begin && i < end) out[(i - begin) * W + w] = lo[u] ^ hi;
+            }
+        }
+        hi ^= tile_step<WMAX>(Bx, Tt, S, w);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // General materialise: z_i = l ^ XOR_m Tab[m][digit m of i].
 // W = 1: 8 byte tables of 256 entries (16 KiB); W > 1: 16 nibble tables of
 // 16 entries, W words each (<= 32 KiB).
@@ -422,6 +500,20 @@ hlf_status launch_tile(const FactorIn &f, uint64_t begin, uint64_t count, T *out
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
 }
 
+template <int WMAX>
+hlf_status launch_wide_tile(const FactorIn &f, uint64_t begin, uint64_t count, uint64_t *out,
+                            int counter, hipStream_t stream) {
+    constexpr int S = kLogTileThreads;
+    const uint64_t end = begin + count;
+    const uint64_t ntiles = (end < begin) ? 1 : ((end - 1) >> S) - (begin >> S) + 1;
+    uint64_t blocks;
+    const uint64_t tpb =
+        tiles_per_block_for(ntiles, (uint64_t)device_cu_count() * kTileBlocksPerCU, &blocks);
+    hipLaunchKernelGGL(enum_wide_tile_kernel<WMAX>, dim3((unsigned)blocks), dim3(kTileThreads), 0,
+                       stream, f, begin, count, out, tpb, counter);
+    return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
+}
+
 template <int WMAX, typename T>
 hlf_status launch_general(const FactorIn &f, uint64_t begin, uint64_t count, T *out, int counter,
                           hipStream_t stream) {
@@ -486,6 +578,12 @@ hlf_status launch_enumerate(const FactorIn &f, uint64_t begin, uint64_t count, i
         return launch_general<1, uint64_t>(f, begin, count, (uint64_t *)out, c, stream);
     }
     uint64_t *o = (uint64_t *)out;
+    if (((uintptr_t)out & 7u) == 0) {
+        if (W <= 2) return launch_wide_tile<2>(f, begin, count, o, c, stream);
+        if (W <= 4) return launch_wide_tile<4>(f, begin, count, o, c, stream);
+        if (W <= 8) return launch_wide_tile<8>(f, begin, count, o, c, stream);
+        return launch_wide_tile<16>(f, begin, count, o, c, stream);
+    }
     if (W <= 2) return launch_general<2, uint64_t>(f, begin, count, o, c, stream);
     if (W <= 4) return launch_general<4, uint64_t>(f, begin, count, o, c, stream);
     if (W <= 8) return launch_general<8, uint64_t>(f, begin, count, o, c, stream);
