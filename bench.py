@@ -359,6 +359,11 @@ def serve_mode(torch):
     return out
 
 
+def _progress(msg):
+    """One progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -484,6 +489,7 @@ def main():
     }
 
     # ---------------- secondary measurements ----------------
+    _progress("headline done")
     if not args.no_modes:
         modes = {}
         # reduce mode, N=6 p=0.5 seeds 0..3, every solution hashed
@@ -552,16 +558,20 @@ def main():
                            "rank": int(F.rank.item()), "samples_per_s": round(65536 / smp_s, 1),
                            "ms_per_65536": round(smp_s * 1e3, 4),
                            "factor_ms_n1024": round(fac_s * 1e3, 4)}
-        modes["tiny"] = tiny_mode(hlf, torch, stream, dev)
-        modes["steady"] = steady_mode(hlf, torch, stream, dev)
-        modes["batch"] = batch_mode(hlf, torch, stream, dev)
-        modes["general"] = general_mode(hlf, torch, stream, dev)
-        modes["verify"] = verify_mode(hlf, torch, stream, dev)
-        modes["serve"] = serve_mode(torch)
+        _progress("reduce and sample modes done")
+        for name, fn in (("tiny", lambda: tiny_mode(hlf, torch, stream, dev)),
+                         ("steady", lambda: steady_mode(hlf, torch, stream, dev)),
+                         ("batch", lambda: batch_mode(hlf, torch, stream, dev)),
+                         ("general", lambda: general_mode(hlf, torch, stream, dev)),
+                         ("verify", lambda: verify_mode(hlf, torch, stream, dev)),
+                         ("serve", lambda: serve_mode(torch))):
+            modes[name] = fn()
+            _progress(f"{name} mode done")
         result["modes"] = modes
 
     # ---------------- CPU baseline: the oracle, on this host ----------------
     if not args.no_cpu_baseline:
+        _progress("cpu baseline (oracle) starting")
         from oracle import c_oracle, hlf_oracle
 
         oracle_F = [hlf_oracle.factor(grid_instance(5, seed=s)) for s in CONFIG2_SEEDS]
