@@ -65,6 +65,188 @@ __global__ __launch_bounds__(SampleShape<WMAX>::kThreads) void sample_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Large n: sampling as a dense product over GF(2) on the matrix cores.
+// Z = C * Bm mod 2, C the num x r coefficient bits, Bm the r x n basis bits:
+// with 0/1 int8 operands the int32 sums of v_mfma_i32_32x32x32_i8 carry the
+// GF(2) product in bit 0 (r <= 1024 < 2^31).  A workgroup owns one group of
+// 128 output bits (4 column chunks of 32); its B operands, in the register
+// layout of the instruction, are built once in LDS (ceil(r/32) x 4 chunks of
+// 64 lanes x 16 bytes).  Each wave multiplies 32 samples by them, the A
+// operand coming straight from the coefficient words: lane l covers sample
+// row l % 32 and the 16 values k = 16*(l / 32) + i of the current 32-wide K
+// chunk (B uses the same k assignment; the sum over k does not depend on it).
+// Accumulator register i of lane l holds row 8*(i/4) + 4*(l/32) + i%4,
+// column l % 32; bit 0 of each is gathered with ballots.
+// ---------------------------------------------------------------------------
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kMfmaJC = 4;       // 32-bit column chunks per workgroup
+constexpr int kMfmaWaves = 8;    // 32 samples per wave per pass
+constexpr int kMfmaMaxKC = HLF_MAX_N / 32;
+
+__device__ __forceinline__ uint32_t bytes_of_nibble(uint32_t nib) {
+    // bit t of nib -> byte t (0 or 1): the partial products of nib with
+    // 2^(7t) land on bit 8t for t < 4 and on distinct other bits, no carries.
+    return (nib * 0x00204081u) & 0x01010101u;
+}
+
+__global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
+    FactorIn f, uint64_t seed, uint64_t num, const uint64_t *__restrict__ coeffs,
+    uint64_t *__restrict__ out) {
+    __shared__ __align__(16) uint32_t Bop[kMfmaMaxKC * kMfmaJC * 64 * 4];  // 128 KiB
+    __shared__ uint64_t BT[128 * 16];                                    // 16 KiB
+    __shared__ uint64_t spread8[256];  // byte v -> 8 bytes, byte t = bit t of v
+    if (*(volatile int32_t *)f.status != HLF_OK) return;
+    const int r = *f.rank;
+    const int W = f.words;
+    const int cg = blockIdx.x;        // words 2cg, 2cg+1 of every sample
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int KC = (r + 31) >> 5;
+    const int KB = (r + 63) >> 6;
+    const int w0 = 2 * cg;
+    const bool has1 = w0 + 1 < W;
+    for (int v = tid; v < 256; v += blockDim.x) {
+        uint64_t e = 0;
+        for (int t = 0; t < 8; ++t) e |= (uint64_t)((v >> t) & 1) << (8 * t);
+        spread8[v] = e;
+    }
+    // Transpose: BT[j * 16 + kb] bit t = bit j (of this group's 128 columns)
+    // of B_{64kb+t}.  A wave takes one (kb, word) tile: lane t holds the word
+    // of row 64kb+t, the ballot of bit b is column b over the 64 rows, and
+    // lane b keeps it.
+    for (int t = wave; t < 2 * KB; t += kMfmaWaves) {
+        const int kb = t >> 1, q = t & 1;
+        const int k = 64 * kb + lane;
+        const uint64_t x = (k < r && (q == 0 || has1)) ? f.basis[(size_t)k * W + w0 + q] : 0ull;
+        uint64_t mine = 0;
+#pragma unroll 8
+        for (int bb = 0; bb < 64; ++bb) {
+            const uint64_t col = __ballot((x >> bb) & 1ull);
+            if (lane == bb) mine = col;
+        }
+        BT[(64 * q + lane) * 16 + kb] = mine;
+    }
+    __syncthreads();
+    // B operand of chunk (kc, jc): lane (h, n) holds bits j = 32jc + n of
+    // B_k, k = 32kc + 16h + i, i < 16, as 16 bytes.
+    for (int t = wave; t < KC * kMfmaJC; t += kMfmaWaves) {
+        const int kc = t / kMfmaJC, jc = t - kc * kMfmaJC;
+        const int h = lane >> 5, nn = lane & 31;
+        const int j = 32 * jc + nn;
+        const uint32_t bits =
+            (uint32_t)(BT[j * 16 + (kc >> 1)] >> (32 * (kc & 1) + 16 * h)) & 0xFFFFu;
+        uint32_t *dst = &Bop[((size_t)t * 64 + lane) * 4];
+        dst[0] = bytes_of_nibble(bits & 0xFu);
+        dst[1] = bytes_of_nibble((bits >> 4) & 0xFu);
+        dst[2] = bytes_of_nibble((bits >> 8) & 0xFu);
+        dst[3] = bytes_of_nibble(bits >> 12);
+    }
+    __syncthreads();
+
+    const uint64_t l0 = f.shift[w0], l1 = has1 ? f.shift[w0 + 1] : 0ull;
+    const int R64 = (r + 63) >> 6;
+    const uint64_t lastmask = (r & 63) ? ((1ull << (r & 63)) - 1ull) : ~0ull;
+    const int h = lane >> 5, m = lane & 31;
+    // Lane t < 32 collects sample row t: accumulator register it, half ht.
+    const int it = 4 * (m >> 3) + (m & 3), ht = (m >> 2) & 1;
+    const uint64_t pass = 32ull * kMfmaWaves;
+    for (uint64_t s0 = (uint64_t)blockIdx.y * pass; s0 < num; s0 += (uint64_t)gridDim.y * pass) {
+        const uint64_t s = s0 + 32ull * wave + (uint64_t)m;  // this lane's A row
+        const bool live = s < num;
+        v16i acc[kMfmaJC];
+#pragma unroll
+        for (int jc = 0; jc < kMfmaJC; ++jc) acc[jc] = v16i{};
+        // Coefficient words 2p, 2p+1 of this row cover K chunks 4p .. 4p+3:
+        // lane half h generates word 2p+h, the halves swap copies.
+        auto words_for = [&](int p, uint64_t (&cw)[2]) {
+            const int q = 2 * p + h;
+            const uint64_t ctr = s * (uint64_t)R64 + (uint64_t)q;
+            uint64_t mine =
+                (live && q < R64) ? (coeffs ? coeffs[ctr] : mix13(seed + (ctr + 1) * kGamma)) : 0ull;
+            if (q == R64 - 1) mine &= lastmask;
+            const uint64_t other = __shfl_xor(mine, 32);
+            cw[0] = h ? other : mine;
+            cw[1] = h ? mine : other;
+        };
+        // A operand of K chunk kc: 16 coefficient bits as bytes, two lookups.
+        auto a_for = [&](int kc, const uint64_t (&cw)[2]) {
+            const uint32_t bits = (uint32_t)(cw[(kc >> 1) & 1] >> (32 * (kc & 1) + 16 * h)) & 0xFFFFu;
+            const uint64_t lo = spread8[bits & 0xFFu], hi = spread8[bits >> 8];
+            v4i a;
+            a[0] = (int)(uint32_t)lo;
+            a[1] = (int)(uint32_t)(lo >> 32);
+            a[2] = (int)(uint32_t)hi;
+            a[3] = (int)(uint32_t)(hi >> 32);
+            return a;
+        };
+        auto b_for = [&](int kc, v4i (&b)[kMfmaJC]) {
+#pragma unroll
+            for (int jc = 0; jc < kMfmaJC; ++jc)
+                b[jc] = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * kMfmaJC + jc) * 64 + lane) * 4]);
+        };
+        uint64_t cw[2];
+        words_for(0, cw);
+        v4i b0[kMfmaJC], b1[kMfmaJC];
+        v4i a0 = a_for(0, cw), a1;
+        b_for(0, b0);
+        // Two K chunks per iteration with alternating operand registers; the
+        // operands of chunk kc+1 are read while chunk kc multiplies.
+        for (int kc = 0; kc < KC; kc += 2) {
+            const bool two = kc + 1 < KC;
+            if (two) {
+                b_for(kc + 1, b1);
+                a1 = a_for(kc + 1, cw);
+            }
+#pragma unroll
+            for (int jc = 0; jc < kMfmaJC; ++jc)
+                acc[jc] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0[jc], acc[jc], 0, 0, 0);
+            if (!two) break;
+            if (kc + 2 < KC) {
+                if (((kc + 2) & 3) == 0) words_for((kc + 2) >> 2, cw);
+                b_for(kc + 2, b0);
+                a0 = a_for(kc + 2, cw);
+            }
+#pragma unroll
+            for (int jc = 0; jc < kMfmaJC; ++jc)
+                acc[jc] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1[jc], acc[jc], 0, 0, 0);
+        }
+        uint32_t word[kMfmaJC];
+#pragma unroll
+        for (int jc = 0; jc < kMfmaJC; ++jc) {
+            uint32_t mine = 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint64_t bm = __ballot(acc[jc][i] & 1);
+                const uint32_t v = ht ? (uint32_t)(bm >> 32) : (uint32_t)bm;
+                if (i == it) mine = v;
+            }
+            word[jc] = mine;
+        }
+        const uint64_t so = s0 + 32ull * wave + (uint64_t)lane;  // row `lane` for lanes < 32
+        if (lane < 32 && so < num) {
+            out[so * W + w0] = (((uint64_t)word[1] << 32) | word[0]) ^ l0;
+            if (has1) out[so * W + w0 + 1] = (((uint64_t)word[3] << 32) | word[2]) ^ l1;
+        }
+    }
+}
+
+hlf_status launch_sample_mfma(const FactorIn &f, uint64_t seed, uint64_t num,
+                              const uint64_t *coeffs, uint64_t *out, hipStream_t stream) {
+    const int W = f.words;
+    const unsigned groups = (unsigned)((W + 1) / 2);
+    const uint64_t passes = (num + 32 * kMfmaWaves - 1) / (32 * kMfmaWaves);
+    // One workgroup per CU fits (the B operands take 128 KiB of LDS); every
+    // workgroup builds them once and loops over passes of 256 samples.
+    uint64_t y = (uint64_t)device_cu_count() / groups;
+    if (y > passes) y = passes;
+    if (y == 0) y = 1;
+    hipLaunchKernelGGL(sample_mfma_kernel, dim3(groups, (unsigned)y), dim3(64 * kMfmaWaves), 0,
+                       stream, f, seed, num, coeffs, out);
+    return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
+}
+
 template <int WMAX>
 hlf_status launch_sample_t(const FactorIn &f, uint64_t seed, uint64_t num,
                            const uint64_t *coeffs, uint64_t *out, hipStream_t stream) {
@@ -85,11 +267,10 @@ hlf_status launch_sample_t(const FactorIn &f, uint64_t seed, uint64_t num,
 hlf_status launch_sample(const FactorIn &f, uint64_t seed, uint64_t num, const uint64_t *coeffs,
                          uint64_t *out, hipStream_t stream) {
     const int W = f.words;
+    if (W >= 4) return launch_sample_mfma(f, seed, num, coeffs, out, stream);
     if (W <= 1) return launch_sample_t<1>(f, seed, num, coeffs, out, stream);
     if (W <= 2) return launch_sample_t<2>(f, seed, num, coeffs, out, stream);
-    if (W <= 4) return launch_sample_t<4>(f, seed, num, coeffs, out, stream);
-    if (W <= 8) return launch_sample_t<8>(f, seed, num, coeffs, out, stream);
-    return launch_sample_t<16>(f, seed, num, coeffs, out, stream);
+    return launch_sample_t<4>(f, seed, num, coeffs, out, stream);
 }
 
 }  // namespace hlf

@@ -208,3 +208,28 @@ def test_sample_uniformity():
     assert vals.size == 64
     chi2 = float(((cnts - 1000.0) ** 2 / 1000.0).sum())
     assert chi2 < 130
+
+
+@pytest.mark.parametrize("name,A,num", [
+    ("grid N=25 (W=10)", grid_instance(25, p=0.5, seed=12), 1000),
+    ("random n=1024 (r=1024)", random_symmetric(1024, 8, 0.5), 333),
+    ("grid N=32 all edges", grid_instance(32, p=1.0, seed=2), 129),
+])
+def test_sample_large_n_matrix_core_path(name, A, num):
+    """n > 192 runs on the matrix cores (int8 products, bit 0 of the sums):
+    exact words against the oracle for the SplitMix64 stream and for explicit
+    coefficients, with sample counts that leave ragged passes."""
+    Fo = O.factor(A)
+    F, st = gpu_factor(A)
+    r, W = Fo["rank"], Fo["words"]
+    print(f"[sample] {name} r={r} num={num}", flush=True)
+    out = hlf.sample(F, 0x5EED, num)
+    torch.cuda.synchronize()
+    assert words_to_ints(hlf.as_uint64(out).reshape(num, W)) == O.sample(Fo, 0x5EED, num)
+    R64 = (r + 63) // 64
+    rng = np.random.default_rng(r)
+    coeffs = rng.integers(-(2**63), 2**63 - 1, size=(num, R64), dtype=np.int64)
+    out = hlf.sample(F, 0, num, coeffs=torch.from_numpy(coeffs).cuda())
+    torch.cuda.synchronize()
+    cints = words_to_ints(coeffs.view(np.uint64))
+    assert words_to_ints(hlf.as_uint64(out).reshape(num, W)) == O.sample(Fo, 0, num, coeffs=cints)
