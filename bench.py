@@ -27,8 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000
-INT8_MFMA_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak.0
+HBM_PEAK_GBS = 8000.0
+INT8_MFMA_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak
 # Full-rate 32-bit VALU lane operations per second: 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
