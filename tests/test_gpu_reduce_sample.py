@@ -233,3 +233,39 @@ def test_sample_large_n_matrix_core_path(name, A, num):
     torch.cuda.synchronize()
     cints = words_to_ints(coeffs.view(np.uint64))
     assert words_to_ints(hlf.as_uint64(out).reshape(num, W)) == O.sample(Fo, 0, num, coeffs=cints)
+
+
+def _one_edge(n, i, j, diag=()):
+    A = np.zeros((n, n), dtype=np.uint8)
+    A[i, j] = A[j, i] = 1
+    for d in diag:
+        A[d, d] = 1
+    return A
+
+
+@pytest.mark.parametrize("name,A", [
+    ("zero n=300 (r=0)", np.zeros((300, 300), dtype=np.uint8)),
+    ("one edge n=300 (r=2)", _one_edge(300, 5, 290)),
+    ("one loop n=257 (r=1)", _one_edge(257, 256, 256)),
+    ("edge + loops n=640 (r=3)", _one_edge(640, 0, 639, diag=(100,))),
+])
+def test_sample_matrix_core_path_small_ranks(name, A):
+    Fo = O.factor(A)
+    F, st = gpu_factor(A)
+    assert st == hlf.HLF_OK
+    num = 300
+    print(f"[sample] {name} r={Fo['rank']}", flush=True)
+    out = hlf.sample(F, 77, num)
+    torch.cuda.synchronize()
+    assert words_to_ints(hlf.as_uint64(out).reshape(num, Fo["words"])) == O.sample(Fo, 77, num)
+
+
+def test_sample_matrix_core_path_gated_on_status():
+    A = np.zeros((300, 300), dtype=np.uint8)
+    A[3, 4] = 1  # not symmetric
+    F, st = gpu_factor(A)
+    assert st == hlf.HLF_ENOTSYM
+    out = torch.full((50, F.words), 0x5A5A, dtype=torch.int64, device="cuda")
+    hlf.sample(F, 1, 50, out=out)
+    torch.cuda.synchronize()
+    assert bool((out == 0x5A5A).all())
