@@ -238,15 +238,18 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
     // every row other than that column's pivot by a linear map over GF(2)
     // (add the pivot's state, plus bit j to the tag, if bit c is set), so
     // the state of such a row is a linear function of its starting slice:
-    // the XOR of the states reached from the 8 unit slices.  Wave 0 keeps
-    // those 8 states in lanes 0-7 and the pivots' own states in lanes 8-15,
-    // and holds the slices of all rows as 8 bit-planes, 16 rows per lane.
-    // At step c the candidates are the unused rows whose slice has odd
-    // parity against w (bit k of w = bit c of unit state k): an XOR of at
-    // most 8 planes and a ballot.  The block ends with every row's tag; the
-    // current value of every row is then its start-of-block value plus the
-    // XOR of the pivot rows in its tag, so one lookup in the table T[tau]
-    // (2^m entries for m pivots) updates every row, pivot rows included.
+    // the XOR of the states reached from the 8 unit slices.  Wave 0 holds the
+    // current slices of all rows as 8 bit-planes, 16 rows per lane, so the
+    // candidates of column c are one plane ANDed with the not-yet-pivot mask
+    // and the pivot is its lowest set bit (a ballot and a readlane); the rows
+    // with bit c then take the pivot's current slice, one XOR per later
+    // plane.  For the tags, lanes 0-7 track the states of the 8 unit slices
+    // and lanes 8-15 the pivots' own states; a pivot's state is the XOR of
+    // the unit states over its starting slice (a DPP reduction).  The block
+    // ends with every row's tag; the current value of every row is then its
+    // start-of-block value plus the XOR of the pivot rows in its tag, so one
+    // lookup in the table T[tau] (2^m entries for m pivots) updates every
+    // row, pivot rows included.
     int r = 0, nfree = 0;
     bool used = false;
     int myk = -1;
