@@ -45,23 +45,6 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
 }
 
 // A value that is the same on every lane, moved to scalar registers.
-// Minimum of v over the 64 lanes of a wave, returned to every lane.  Needs
-// all lanes active.  Four DPP row_shr steps leave the minimum of each row of
-// 16 lanes in its last lane (a disabled source lane contributes the identity
-// 0xFFFFFFFF through `old`); the four row minima are combined on the SALU.
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-    constexpr int kMax = (int)0xFFFFFFFFu;
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(kMax, (int)v, 0x111, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(kMax, (int)v, 0x112, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(kMax, (int)v, 0x114, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(kMax, (int)v, 0x118, 0xF, 0xF, false));
-    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
-    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
-    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
-    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-    return min(min(a, b), min(c, d));
-}
-
 // XOR of v over lanes 0..7 of a wave, returned to every lane.  Needs all
 // lanes active.  Three DPP row_shr steps leave the XOR of lanes 0..7 in lane
 // 7 (a disabled source lane contributes the identity 0 through `old`).
