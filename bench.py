@@ -335,7 +335,7 @@ def serve_mode(torch):
         return [Request(rid=k, A=q["A"], seed=q["seed"], arrival=q["t"])
                 for k, q in enumerate(serve_requests(count, rate, master_seed=seed))]
 
-    Server(slots=8).run(reqs(1000.0, 99)[:16], realtime=False)  # warm-up
+    Server(slots=8).run(reqs(1000.0, 99), realtime=False)  # warm-up to steady state
     srv = Server(slots=8)
     t0 = time.perf_counter()
     res = srv.run(reqs(1000.0, 1), realtime=False)
