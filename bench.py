@@ -42,8 +42,8 @@ REDUCE_VALU_OPS_PER_SOLUTION = 17
 # dispatch), each scaled by what the same counter reads for a plain 256 MiB
 # device copy (WRITE_SIZE 262144 KiB -> x1.0, FETCH_SIZE 131085 KiB -> x2.0).
 # Valid only for the kernel sources it was taken on (sha256 prefix below).
-ENUM_TRAFFIC = {"src_sha256_16": "138fd821f654234a", "fetch_kib_raw": 75.9, "fetch_scale": 2.0,
-                "write_kib_raw": 688734.6, "write_scale": 1.0}
+ENUM_TRAFFIC = {"src_sha256_16": "e4509d10fbc96059", "fetch_kib_raw": 76.1, "fetch_scale": 2.0,
+                "write_kib_raw": 688833.2, "write_scale": 1.0}
 ENUM_TRAFFIC_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/batch.hip",
                         "paper_2103_00693_amd/csrc/factor_wave.h",
                         "paper_2103_00693_amd/csrc/hlf_device.h")
