@@ -4,8 +4,8 @@
 //   batch_factor_kernel<WMAX>   pack + validate + factor, one wavefront (a
 //                               64-thread workgroup) per instance, n <= 64*WMAX.
 //   batch_enum_kernel<T>        materialise for up to kMaxEnumTasks instances
-//                               in one launch; blocks are dealt to instances in
-//                               proportion to their tiles.
+//                               in one launch; each workgroup takes a short
+//                               contiguous tile range of one instance.
 //   batch_reduce_kernel<WMAX>   persistent: each wavefront first takes factor
 //                               tasks from a device counter; an instance with
 //                               r <= max_rank then claims a contiguous block of
@@ -713,7 +713,6 @@ hlf_status batch_enumerate_impl(hlf_batch b, int32_t num, const int32_t *inst,
             if (s != HLF_OK) return s;
         }
     }
-    const uint64_t target_blocks = (uint64_t)hlf::device_cu_count() * hlf::kTileBlocksPerCU;
     bool job_done = job == nullptr;
     for (size_t g = 0; g < fast.size() || !job_done; g += hlf::kMaxEnumTasks) {
         const size_t m = g < fast.size() ? std::min<size_t>(hlf::kMaxEnumTasks, fast.size() - g) : 0;
@@ -725,7 +724,7 @@ hlf_status batch_enumerate_impl(hlf_batch b, int32_t num, const int32_t *inst,
             tiles[j] = ((end - 1) >> S) - (begin[k] >> S) + 1;
             total += tiles[j];
         }
-        const uint64_t tpb = std::max<uint64_t>(1, (total + target_blocks - 1) / target_blocks);
+        const uint64_t tpb = hlf::materialise_tiles_per_block(total, hlf::kTileBytes);
         hlf::EnumTasks tasks;
         std::memset(&tasks, 0, sizeof(tasks));
         tasks.num = (int)m;

@@ -473,11 +473,19 @@ __global__ void zero_outputs_kernel(FactorIn f, uint64_t begin, uint64_t count, 
         for (int w = threadIdx.x; w < W; w += blockDim.x) xorfold[w] = 0;
 }
 
-uint64_t tiles_per_block_for(uint64_t ntiles, uint64_t max_blocks, uint64_t *blocks) {
-    uint64_t b = ntiles < max_blocks ? ntiles : max_blocks;
+// Even split of ntiles over at most max_units units: tiles per unit.
+uint64_t tiles_per_unit_for(uint64_t ntiles, uint64_t max_units, uint64_t *units) {
+    uint64_t b = ntiles < max_units ? ntiles : max_units;
     if (b == 0) b = 1;
-    const uint64_t tpb = (ntiles + b - 1) / b;
-    *blocks = (ntiles + tpb - 1) / tpb;
+    const uint64_t tpu = (ntiles + b - 1) / b;
+    *units = (ntiles + tpu - 1) / tpu;
+    return tpu;
+}
+
+// Materialise launches: materialise_tiles_per_block tiles per workgroup.
+uint64_t tiles_per_block_for(uint64_t ntiles, uint64_t tile_bytes, uint64_t *blocks) {
+    const uint64_t tpb = materialise_tiles_per_block(ntiles, tile_bytes);
+    *blocks = ntiles ? (ntiles + tpb - 1) / tpb : 1;
     return tpb;
 }
 
@@ -493,8 +501,7 @@ hlf_status launch_tile(const FactorIn &f, uint64_t begin, uint64_t count, T *out
         ntiles = ((end - 1) >> S) - (begin >> S) + 1;
     }
     uint64_t blocks;
-    const uint64_t tpb =
-        tiles_per_block_for(ntiles, (uint64_t)device_cu_count() * kTileBlocksPerCU, &blocks);
+    const uint64_t tpb = tiles_per_block_for(ntiles, kTileBytes, &blocks);
     hipLaunchKernelGGL(enum_tile_kernel<T>, dim3((unsigned)blocks), dim3(kTileThreads), 0, stream,
                        f, begin, count, out, tpb, counter);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
@@ -507,8 +514,7 @@ hlf_status launch_wide_tile(const FactorIn &f, uint64_t begin, uint64_t count, u
     const uint64_t end = begin + count;
     const uint64_t ntiles = (end < begin) ? 1 : ((end - 1) >> S) - (begin >> S) + 1;
     uint64_t blocks;
-    const uint64_t tpb =
-        tiles_per_block_for(ntiles, (uint64_t)device_cu_count() * kTileBlocksPerCU, &blocks);
+    const uint64_t tpb = tiles_per_block_for(ntiles, 8ull * (uint64_t)f.words << S, &blocks);
     hipLaunchKernelGGL(enum_wide_tile_kernel<WMAX>, dim3((unsigned)blocks), dim3(kTileThreads), 0,
                        stream, f, begin, count, out, tpb, counter);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
@@ -548,7 +554,7 @@ hlf_status launch_reduce_wave(const FactorIn &f, uint64_t begin, uint64_t count,
     const uint64_t end = begin + count;
     const uint64_t ntiles = (end < begin) ? 1 : ((end - 1) >> S) - (begin >> S) + 1;
     uint64_t waves;
-    const uint64_t tpw = tiles_per_block_for(ntiles, (uint64_t)device_cu_count() * 32, &waves);
+    const uint64_t tpw = tiles_per_unit_for(ntiles, (uint64_t)device_cu_count() * 32, &waves);
     const uint64_t blocks = (waves + 3) / 4;
     hipLaunchKernelGGL(reduce_wave_kernel<WW>, dim3((unsigned)blocks), dim3(256), 0, stream, f,
                        begin, count, tpw, counts, hash, xorfold);
@@ -599,8 +605,7 @@ hlf_status launch_circuit(const FactorIn &f, const int32_t *pivots, const uint64
         constexpr int S = tile_shift<T>();
         const uint64_t ntiles = (end < begin) ? 1 : ((end - 1) >> S) - (begin >> S) + 1;
         uint64_t blocks;
-        const uint64_t tpb =
-            tiles_per_block_for(ntiles, (uint64_t)device_cu_count() * kTileBlocksPerCU, &blocks);
+        const uint64_t tpb = tiles_per_block_for(ntiles, kTileBytes, &blocks);
         hipLaunchKernelGGL(circuit_tile_kernel<T>, dim3((unsigned)blocks), dim3(kTileThreads), 0,
                            stream, f, pivots, rows, N, begin, count, (T *)out, tpb);
         return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;

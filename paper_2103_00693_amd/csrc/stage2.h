@@ -92,9 +92,32 @@ struct Vec {
 // tile, so a tile holds 1024*V solutions.
 constexpr int kTileThreads = 1024;
 constexpr int kLogTileThreads = 10;
-// Workgroups per CU of a materialise launch (more workgroups than resident
-// slots: the dispatcher balances the tail).
+// Workgroups per CU of the one-launch solve kernel (more workgroups than
+// resident slots: the dispatcher balances the tail).
 constexpr int kTileBlocksPerCU = 16;
+// Materialise kernels give each workgroup a short contiguous range of about
+// kBlockBytes of output, and a launch holds many more workgroups than fit on
+// the device, so the resident ones are at different points of their ranges
+// (resident workgroups that write in step at a fixed stride lose 5-15% of
+// the write bandwidth).  Longer ranges only for grids beyond kMaxTileBlocks.
+constexpr uint64_t kBlockBytes = 128ull << 10;
+constexpr uint64_t kMaxTileBlocks = 1ull << 30;
+
+// Tiles per workgroup for a materialise launch over ntiles tiles of
+// tile_bytes bytes each; a launch too small to give every CU two workgroups
+// at that size is spread thinner.
+inline uint64_t materialise_tiles_per_block(uint64_t ntiles, uint64_t tile_bytes) {
+    uint64_t want = kBlockBytes / tile_bytes ? kBlockBytes / tile_bytes : 1;
+    const uint64_t spread = 2ull * (uint64_t)device_cu_count();
+    const uint64_t thin = (ntiles + spread - 1) / spread;
+    if (thin < want) want = thin ? thin : 1;
+    const uint64_t need = (ntiles + kMaxTileBlocks - 1) / kMaxTileBlocks;
+    return need > want ? need : want;
+}
+
+// Bytes of one tile of the W = 1 materialise kernels (one 16-byte store per
+// thread).
+constexpr uint64_t kTileBytes = 16ull * kTileThreads;
 
 template <typename T>
 __host__ __device__ constexpr int tile_shift() {
