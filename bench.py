@@ -37,13 +37,21 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (its GF(2)-linear first step is applied per lane and per tile), 14 for the
 # rest of mix13 (2 x [3 multiplies + add3], 2 x [64-bit shift + 2 XOR]), 1 add.
 REDUCE_VALU_OPS_PER_SOLUTION = 17
+# Measured: rocprofv3 --pmc SQ_INSTS_VALU over the four timed reduce launches
+# (ranks 30, 29, 32, 32): 3,031,564,172 wave instructions x 64 lanes /
+# 10,200,547,328 solutions = 19.02 lane operations per solution (the full-tile
+# loop plus per-tile and per-wave work).  The roofline uses it while the
+# kernel's sources are the measured ones, else the loop count above.
+REDUCE_VALU_MEASURED = {"src_sha256_16": "22f843e5b16533f9", "ops_per_solution": 19.02}
+REDUCE_VALU_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/enumerate.hip",
+                       "paper_2103_00693_amd/csrc/hlf_device.h")
 # HBM traffic of one batch_enum_kernel<uint32_t, overlap> launch of the headline step,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch), each scaled by what the same counter reads for a plain 256 MiB
 # device copy (WRITE_SIZE 262144 KiB -> x1.0, FETCH_SIZE 131085 KiB -> x2.0).
 # Valid only for the kernel sources it was taken on (sha256 prefix below).
-ENUM_TRAFFIC = {"src_sha256_16": "e4509d10fbc96059", "fetch_kib_raw": 76.1, "fetch_scale": 2.0,
-                "write_kib_raw": 688833.2, "write_scale": 1.0}
+ENUM_TRAFFIC = {"src_sha256_16": "50fc5b92ce3c7fa4", "fetch_kib_raw": 76.0, "fetch_scale": 2.0,
+                "write_kib_raw": 688643.2, "write_scale": 1.0}
 ENUM_TRAFFIC_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/batch.hip",
                         "paper_2103_00693_amd/csrc/factor_wave.h",
                         "paper_2103_00693_amd/csrc/hlf_device.h")
@@ -58,21 +66,37 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-modes", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--only", default="",
+                    help="comma-separated secondary modes to run (reduce, sample, tiny, steady, batch, "
+                         "general, verify, serve); default all")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (for HBM counter scaling)")
     return ap.parse_args()
 
 
-def enum_traffic_bytes():
-    """Measured HBM bytes per launch of the headline kernel, or None if its
-    sources changed since the counters were taken."""
+def _sources_sha256_16(paths):
     import hashlib
 
     h = hashlib.sha256()
-    for rel in ENUM_TRAFFIC_SOURCES:
+    for rel in paths:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest()[:16] != ENUM_TRAFFIC["src_sha256_16"]:
+    return h.hexdigest()[:16]
+
+
+def reduce_valu_ops_per_solution():
+    """(VALU lane operations per solution, how it was obtained) for the reduce
+    roofline: the counter measurement while the sources match, else the
+    count of the full-tile loop."""
+    if _sources_sha256_16(REDUCE_VALU_SOURCES) == REDUCE_VALU_MEASURED["src_sha256_16"]:
+        return REDUCE_VALU_MEASURED["ops_per_solution"], "SQ_INSTS_VALU x 64 / solutions (rocprofv3)"
+    return REDUCE_VALU_OPS_PER_SOLUTION, "full-tile loop instruction count (assembly)"
+
+
+def enum_traffic_bytes():
+    """Measured HBM bytes per launch of the headline kernel, or None if its
+    sources changed since the counters were taken."""
+    if _sources_sha256_16(ENUM_TRAFFIC_SOURCES) != ENUM_TRAFFIC["src_sha256_16"]:
         return None
     t = ENUM_TRAFFIC
     return int(1024 * (t["fetch_kib_raw"] * t["fetch_scale"] + t["write_kib_raw"] * t["write_scale"]))
@@ -493,85 +517,96 @@ def main():
     _progress("headline done")
     if not args.no_modes:
         modes = {}
-        # reduce mode, N=6 p=0.5 seeds 0..3, every solution hashed
-        red = []
-        with torch.cuda.stream(stream):
-            for s in CONFIG3_SEEDS:
-                A = torch.from_numpy(grid_instance(6, p=0.5, seed=s)).to(dev)
-                rows, st = hlf.pack_dense(A, stream=stream)
-                F = hlf.factor(rows, 36, stream=stream)
-                red.append(F)
-        stream.synchronize()
-        ranks = []
-        outs = []
-        for F in red:
+        def reduce_block():
+            # reduce mode, N=6 p=0.5 seeds 0..3, every solution hashed
+            red = []
+            with torch.cuda.stream(stream):
+                for s in CONFIG3_SEEDS:
+                    A = torch.from_numpy(grid_instance(6, p=0.5, seed=s)).to(dev)
+                    rows, st = hlf.pack_dense(A, stream=stream)
+                    F = hlf.factor(rows, 36, stream=stream)
+                    red.append(F)
+            stream.synchronize()
+            ranks = []
+            outs = []
+            for F in red:
+                F.check()
+                ranks.append(int(F.rank.item()))
+                outs.append((torch.zeros(36, dtype=torch.int64, device=dev),
+                             torch.zeros(1, dtype=torch.int64, device=dev),
+                             torch.zeros(1, dtype=torch.int64, device=dev)))
+            for F, r, o in zip(red, ranks, outs):  # warm-up
+                hlf.enumerate_reduce(F, 0, 1 << r, counts=o[0], hash_out=o[1], xorfold=o[2], stream=stream)
+            stream.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for F, r, o in zip(red, ranks, outs):
+                hlf.enumerate_reduce(F, 0, 1 << r, counts=o[0], hash_out=o[1], xorfold=o[2], stream=stream)
+            e1.record(stream)
+            stream.synchronize()
+            red_s = e0.elapsed_time(e1) * 1e-3
+            red_sol = sum(1 << r for r in ranks)
+            rate = red_sol / red_s
+            per_sol, how = reduce_valu_ops_per_solution()
+            ops = rate * per_sol / 1e12
+            return {
+                "workload": "N=6 grid (n=36), edges p=0.5, seeds 0-3: counts + hash + xorfold over all 2^r",
+                "ranks": ranks,
+                "value": round(rate / 1e9, 2),
+                "unit": "G solutions/s",
+                "roofline": {"bound": "alu", "kernel": "reduce_wave_kernel<1>",
+                             "achieved": round(ops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                             "unit": "T VALU instr-lane-ops/s", "frac": round(ops / VALU_PEAK_TOPS, 4),
+                             "valu_ops_per_solution": per_sol, "valu_ops_source": how},
+            }
+
+        def sample_block():
+            # sampling at n = 1024
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            A = torch.from_numpy(grid_instance(32, p=0.5, seed=17)).to(dev)
+            rows, st = hlf.pack_dense(A, stream=stream)
+            F = hlf.factor(rows, 1024, stream=stream)
+            out = torch.empty((65536, 16), dtype=torch.int64, device=dev)
+            hlf.sample(F, 1, 65536, out=out, stream=stream)
+            stream.synchronize()
             F.check()
-            ranks.append(int(F.rank.item()))
-            outs.append((torch.zeros(36, dtype=torch.int64, device=dev),
-                         torch.zeros(1, dtype=torch.int64, device=dev),
-                         torch.zeros(1, dtype=torch.int64, device=dev)))
-        for F, r, o in zip(red, ranks, outs):  # warm-up
-            hlf.enumerate_reduce(F, 0, 1 << r, counts=o[0], hash_out=o[1], xorfold=o[2], stream=stream)
-        stream.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for F, r, o in zip(red, ranks, outs):
-            hlf.enumerate_reduce(F, 0, 1 << r, counts=o[0], hash_out=o[1], xorfold=o[2], stream=stream)
-        e1.record(stream)
-        stream.synchronize()
-        red_s = e0.elapsed_time(e1) * 1e-3
-        red_sol = sum(1 << r for r in ranks)
-        rate = red_sol / red_s
-        ops = rate * REDUCE_VALU_OPS_PER_SOLUTION / 1e12
-        modes["reduce"] = {
-            "workload": "N=6 grid (n=36), edges p=0.5, seeds 0-3: counts + hash + xorfold over all 2^r",
-            "ranks": ranks,
-            "value": round(rate / 1e9, 2),
-            "unit": "G solutions/s",
-            "roofline": {"bound": "alu", "kernel": "reduce_wave_kernel<1>",
-                         "achieved": round(ops, 2), "peak": round(VALU_PEAK_TOPS, 2),
-                         "unit": "T VALU instr-lane-ops/s", "frac": round(ops / VALU_PEAK_TOPS, 4),
-                         "valu_ops_per_solution": REDUCE_VALU_OPS_PER_SOLUTION},
-        }
-        # sampling at n = 1024
-        A = torch.from_numpy(grid_instance(32, p=0.5, seed=17)).to(dev)
-        rows, st = hlf.pack_dense(A, stream=stream)
-        F = hlf.factor(rows, 1024, stream=stream)
-        out = torch.empty((65536, 16), dtype=torch.int64, device=dev)
-        hlf.sample(F, 1, 65536, out=out, stream=stream)
-        stream.synchronize()
-        F.check()
-        e0.record(stream)
-        reps = 5
-        for k in range(reps):
-            hlf.sample(F, k, 65536, out=out, stream=stream)
-        e1.record(stream)
-        stream.synchronize()
-        smp_s = e0.elapsed_time(e1) * 1e-3 / reps
-        e0.record(stream)
-        for k in range(reps):
-            hlf.factor(rows, 1024, F, stream=stream)
-        e1.record(stream)
-        stream.synchronize()
-        fac_s = e0.elapsed_time(e1) * 1e-3 / reps
-        rk = int(F.rank.item())
-        ops = 2.0 * 65536 * rk * 1024 / smp_s / 1e12  # int8 MACs of the GF(2) product
-        modes["sample"] = {"workload": "N=32 grid (n=1024), p=0.5: 65536 uniform samples",
-                           "rank": rk, "samples_per_s": round(65536 / smp_s, 1),
-                           "ms_per_65536": round(smp_s * 1e3, 4),
-                           "roofline": {"bound": "mfma", "kernel": "sample_mfma_kernel (int8 32x32x32)",
-                                        "achieved": round(ops, 1), "peak": INT8_MFMA_PEAK_TOPS,
-                                        "unit": "TOP/s", "frac": round(ops / INT8_MFMA_PEAK_TOPS, 4),
-                                        "ops_per_sample": 2 * rk * 1024},
-                           "factor_ms_n1024": round(fac_s * 1e3, 4)}
-        _progress("reduce and sample modes done")
-        for name, fn in (("tiny", lambda: tiny_mode(hlf, torch, stream, dev)),
+            e0.record(stream)
+            reps = 5
+            for k in range(reps):
+                hlf.sample(F, k, 65536, out=out, stream=stream)
+            e1.record(stream)
+            stream.synchronize()
+            smp_s = e0.elapsed_time(e1) * 1e-3 / reps
+            e0.record(stream)
+            for k in range(reps):
+                hlf.factor(rows, 1024, F, stream=stream)
+            e1.record(stream)
+            stream.synchronize()
+            fac_s = e0.elapsed_time(e1) * 1e-3 / reps
+            rk = int(F.rank.item())
+            ops = 2.0 * 65536 * rk * 1024 / smp_s / 1e12  # int8 MACs of the GF(2) product
+            return {"workload": "N=32 grid (n=1024), p=0.5: 65536 uniform samples",
+                    "rank": rk, "samples_per_s": round(65536 / smp_s, 1),
+                    "ms_per_65536": round(smp_s * 1e3, 4),
+                    "roofline": {"bound": "mfma", "kernel": "sample_mfma_kernel (int8 32x32x32)",
+                                 "achieved": round(ops, 1), "peak": INT8_MFMA_PEAK_TOPS,
+                                 "unit": "TOP/s", "frac": round(ops / INT8_MFMA_PEAK_TOPS, 4),
+                                 "ops_per_sample": 2 * rk * 1024},
+                    "factor_ms_n1024": round(fac_s * 1e3, 4)}
+
+        only = set(x for x in args.only.split(",") if x)
+        for name, fn in (("reduce", reduce_block),
+                         ("sample", sample_block),
+                         ("tiny", lambda: tiny_mode(hlf, torch, stream, dev)),
                          ("steady", lambda: steady_mode(hlf, torch, stream, dev)),
                          ("batch", lambda: batch_mode(hlf, torch, stream, dev)),
                          ("general", lambda: general_mode(hlf, torch, stream, dev)),
                          ("verify", lambda: verify_mode(hlf, torch, stream, dev)),
                          ("serve", lambda: serve_mode(torch))):
+            if only and name not in only:
+                continue
             modes[name] = fn()
             _progress(f"{name} mode done")
         result["modes"] = modes

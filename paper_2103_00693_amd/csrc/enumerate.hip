@@ -507,6 +507,11 @@ hlf_status launch_tile(const FactorIn &f, uint64_t begin, uint64_t count, T *out
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
 }
 
+// The multi-word kernel's workgroups build per-word tables before their first
+// store, so they take ranges kWideRangeFactor times longer than the W = 1
+// kernels (passed as a smaller nominal tile size).
+constexpr uint64_t kWideRangeFactor = 2;
+
 template <int WMAX>
 hlf_status launch_wide_tile(const FactorIn &f, uint64_t begin, uint64_t count, uint64_t *out,
                             int counter, hipStream_t stream) {
@@ -514,7 +519,7 @@ hlf_status launch_wide_tile(const FactorIn &f, uint64_t begin, uint64_t count, u
     const uint64_t end = begin + count;
     const uint64_t ntiles = (end < begin) ? 1 : ((end - 1) >> S) - (begin >> S) + 1;
     uint64_t blocks;
-    const uint64_t tpb = tiles_per_block_for(ntiles, 8ull * (uint64_t)f.words << S, &blocks);
+    const uint64_t tpb = tiles_per_block_for(ntiles, (8ull * (uint64_t)f.words << S) / kWideRangeFactor, &blocks);
     hipLaunchKernelGGL(enum_wide_tile_kernel<WMAX>, dim3((unsigned)blocks), dim3(kTileThreads), 0,
                        stream, f, begin, count, out, tpb, counter);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;

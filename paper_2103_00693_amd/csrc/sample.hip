@@ -73,11 +73,13 @@ __global__ __launch_bounds__(SampleShape<WMAX>::kThreads) void sample_kernel(
 // 128 output bits (4 column chunks of 32); its B operands, in the register
 // layout of the instruction, are built once in LDS (ceil(r/32) x 4 chunks of
 // 64 lanes x 16 bytes).  Each wave multiplies 32 samples by them, the A
-// operand coming straight from the coefficient words: lane l covers sample
-// row l % 32 and the 16 values k = 16*(l / 32) + i of the current 32-wide K
-// chunk (B uses the same k assignment; the sum over k does not depend on it).
-// Accumulator register i of lane l holds row 8*(i/4) + 4*(l/32) + i%4,
-// column l % 32; bit 0 of each is gathered with ballots.
+// operand coming straight from the coefficient words.  Within a 32-wide K
+// chunk, byte t of operand dword d of lane l stands for k = 8t + d + 4h,
+// h = l / 32 (B uses the same assignment; the sum over k does not depend on
+// it): if y holds the chunk's 32 bits, dword d is (y >> (d + 4h)) &
+// 0x01010101, a shift and a mask for A and B alike, and lane l covers sample
+// row l % 32.  Accumulator register i of lane l holds row 8*(i/4) +
+// 4*(l/32) + i%4, column l % 32; bit 0 of each is gathered with ballots.
 // ---------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
@@ -86,10 +88,9 @@ constexpr int kMfmaJC = 4;       // 32-bit column chunks per workgroup
 constexpr int kMfmaWaves = 8;    // 32 samples per wave per pass
 constexpr int kMfmaMaxKC = HLF_MAX_N / 32;
 
-__device__ __forceinline__ uint32_t bytes_of_nibble(uint32_t nib) {
-    // bit t of nib -> byte t (0 or 1): the partial products of nib with
-    // 2^(7t) land on bit 8t for t < 4 and on distinct other bits, no carries.
-    return (nib * 0x00204081u) & 0x01010101u;
+// Operand dword d of lane half h for the chunk bits y: byte t = bit 8t+d+4h.
+__device__ __forceinline__ uint32_t chunk_bytes(uint32_t y, int d, int h) {
+    return (y >> (d + 4 * h)) & 0x01010101u;
 }
 
 __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
@@ -97,7 +98,6 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
     uint64_t *__restrict__ out) {
     __shared__ __align__(16) uint32_t Bop[kMfmaMaxKC * kMfmaJC * 64 * 4];  // 128 KiB
     __shared__ uint64_t BT[128 * 16];                                    // 16 KiB
-    __shared__ uint64_t spread8[256];  // byte v -> 8 bytes, byte t = bit t of v
     if (*(volatile int32_t *)f.status != HLF_OK) return;
     const int r = *f.rank;
     const int W = f.words;
@@ -107,11 +107,6 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
     const int KB = (r + 63) >> 6;
     const int w0 = 2 * cg;
     const bool has1 = w0 + 1 < W;
-    for (int v = tid; v < 256; v += blockDim.x) {
-        uint64_t e = 0;
-        for (int t = 0; t < 8; ++t) e |= (uint64_t)((v >> t) & 1) << (8 * t);
-        spread8[v] = e;
-    }
     // Transpose: BT[j * 16 + kb] bit t = bit j (of this group's 128 columns)
     // of B_{64kb+t}.  A wave takes one (kb, word) tile: lane t holds the word
     // of row 64kb+t, the ballot of bit b is column b over the 64 rows, and
@@ -129,19 +124,16 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
         BT[(64 * q + lane) * 16 + kb] = mine;
     }
     __syncthreads();
-    // B operand of chunk (kc, jc): lane (h, n) holds bits j = 32jc + n of
-    // B_k, k = 32kc + 16h + i, i < 16, as 16 bytes.
+    // B operand of chunk (kc, jc): lane (h, n), dword d, byte t holds bit
+    // j = 32jc + n of B_k, k = 32kc + 8t + d + 4h.
     for (int t = wave; t < KC * kMfmaJC; t += kMfmaWaves) {
         const int kc = t / kMfmaJC, jc = t - kc * kMfmaJC;
         const int h = lane >> 5, nn = lane & 31;
         const int j = 32 * jc + nn;
-        const uint32_t bits =
-            (uint32_t)(BT[j * 16 + (kc >> 1)] >> (32 * (kc & 1) + 16 * h)) & 0xFFFFu;
+        const uint32_t y = (uint32_t)(BT[j * 16 + (kc >> 1)] >> (32 * (kc & 1)));
         uint32_t *dst = &Bop[((size_t)t * 64 + lane) * 4];
-        dst[0] = bytes_of_nibble(bits & 0xFu);
-        dst[1] = bytes_of_nibble((bits >> 4) & 0xFu);
-        dst[2] = bytes_of_nibble((bits >> 8) & 0xFu);
-        dst[3] = bytes_of_nibble(bits >> 12);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) dst[d] = chunk_bytes(y, d, h);
     }
     __syncthreads();
 
@@ -170,15 +162,12 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
             cw[0] = h ? other : mine;
             cw[1] = h ? mine : other;
         };
-        // A operand of K chunk kc: 16 coefficient bits as bytes, two lookups.
+        // A operand of K chunk kc: this lane half's 16 coefficient bits as bytes.
         auto a_for = [&](int kc, const uint64_t (&cw)[2]) {
-            const uint32_t bits = (uint32_t)(cw[(kc >> 1) & 1] >> (32 * (kc & 1) + 16 * h)) & 0xFFFFu;
-            const uint64_t lo = spread8[bits & 0xFFu], hi = spread8[bits >> 8];
+            const uint32_t y = (uint32_t)(cw[(kc >> 1) & 1] >> (32 * (kc & 1)));
             v4i a;
-            a[0] = (int)(uint32_t)lo;
-            a[1] = (int)(uint32_t)(lo >> 32);
-            a[2] = (int)(uint32_t)hi;
-            a[3] = (int)(uint32_t)(hi >> 32);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) a[d] = (int)chunk_bytes(y, d, h);
             return a;
         };
         auto b_for = [&](int kc, v4i (&b)[kMfmaJC]) {
