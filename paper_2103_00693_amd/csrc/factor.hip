@@ -172,8 +172,9 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
     __shared__ int piv[64 * WMAX];
     __shared__ int freec[64 * WMAX];
     __shared__ int qacc[64 * WMAX];
-    __shared__ uint64_t planes[8 * 16];
     __shared__ __align__(16) uint8_t sl8[1024];
+    __shared__ uint16_t pivmark[64 * WMAX];  // block * 8 + j for the block's j-th pivot row
+    __shared__ uint32_t ttab[32];            // tag of a slice: ttab[low nibble] ^ ttab[16 + high]
     __shared__ __align__(16) uint32_t blkstate[16];
     __shared__ __align__(16) int pivinfo[8];
     __shared__ int blk[2];
@@ -196,6 +197,7 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
         mat[w * NP + tid] = row[w];
     }
     if (tid < WMAX) shiftw[tid] = 0;
+    pivmark[tid] = 0xFFFFu;
     if (tid == 0) {
         flag_bad = 0;
         flag_internal = 0;
@@ -257,31 +259,42 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
     if (wave == 0)
         for (int b = 0; b < 16; ++b)
             if (16 * lane + b < n) unused16 |= 1u << b;
+    uint64_t cur = row[0];  // word c0 / 64 of this row, kept current
     for (int c0 = 0; c0 < n; c0 += 8) {
         const int kb = (n - c0) < 8 ? (n - c0) : 8;
         const int cw = c0 >> 6;
-        uint64_t word = 0;
+        const int blkno = c0 >> 3;
+        if (cw && (c0 & 63) == 0) {
 #pragma unroll
-        for (int w = 0; w < WMAX; ++w)
-            if (w == cw) word = row[w];
-        const uint32_t sl = (uint32_t)(word >> (c0 & 63)) & 0xFFu;
-        sl8[tid] = (uint8_t)sl;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint64_t pk = __ballot((sl >> k) & 1u);
-            if (lane == 0) planes[k * 16 + wave] = pk;
+            for (int w = 0; w < WMAX; ++w)
+                if (w == cw) cur = row[w];
         }
+        const uint32_t sl = (uint32_t)(cur >> (c0 & 63)) & 0xFFu;
+        sl8[tid] = (uint8_t)sl;
         __syncthreads();
 
         if (wave == 0) {
             // cp[u]: bit b of lane l <=> bit u of the current slice of row
-            // 16l+b.  Lanes past the last row hold stale words; their rows are
-            // never candidates (unused16 is 0 there).
-            const int gw = lane >> 2, gs = 16 * (lane & 3);
+            // 16l+b: the 16 slices of the lane, as two 8x8 bit matrices (byte
+            // = row, bit = column), transposed with three delta swaps.  Lanes
+            // past the last row hold stale bytes; their rows are never
+            // candidates (unused16 is 0 there).
+            const u32x4 sq = *reinterpret_cast<const u32x4 *>(&sl8[16 * lane]);
+            auto transpose8 = [](uint64_t x) {
+                uint64_t t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+                x ^= t ^ (t << 7);
+                t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+                x ^= t ^ (t << 14);
+                t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+                x ^= t ^ (t << 28);
+                return x;
+            };
+            const uint64_t p0 = transpose8(((uint64_t)sq.y << 32) | sq.x);
+            const uint64_t p1 = transpose8(((uint64_t)sq.w << 32) | sq.z);
             uint32_t cp[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) cp[k] = (uint32_t)(planes[k * 16 + gw] >> gs) & 0xFFFFu;
-            const u32x4 sq = *reinterpret_cast<const u32x4 *>(&sl8[16 * lane]);
+            for (int k = 0; k < 8; ++k)
+                cp[k] = (uint32_t)((p0 >> (8 * k)) & 0xFFu) | ((uint32_t)((p1 >> (8 * k)) & 0xFFu) << 8);
             // Lane k < 8: state of unit slice e_k (slice | tag << 8); lane 8+j:
             // state of pivot j after its own step.
             uint32_t st = (lane < 8) ? (1u << lane) : 0u;
@@ -323,11 +336,25 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
                 if (lane == 8 + m) st = xr;
                 if (lane == 0) {
                     piv[r + m] = c0 + t;
-                    pivinfo[m] = 16 * L + b;
+                    pivmark[16 * L + b] = (uint16_t)(8 * blkno + m);
                 }
                 ++m;
             }
-            if (lane < 16) blkstate[lane] = (st >> 8) & 0xFFu;
+            // Tag of a row = XOR of the unit tags over its starting slice,
+            // as two 16-entry tables (low and high nibble): lane l < 32 fills
+            // entry l & 15 of table l >> 4.
+            uint32_t us[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) us[k] = ((uint32_t)__builtin_amdgcn_readlane((int)st, k) >> 8) & 0xFFu;
+            if (lane < 32) {
+                const int hi = lane >> 4, e = lane & 15;
+                uint32_t v = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if ((e >> k) & 1) v ^= hi ? us[4 + k] : us[k];
+                ttab[lane] = v;
+            }
+            if (lane >= 8 && lane < 16) blkstate[lane] = (st >> 8) & 0xFFu;
             if (lane == 0) {
                 blk[0] = m;
                 blk[1] = nfree;
@@ -338,28 +365,13 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
         nfree = blk[1];
         uint32_t tau = 0;
         if (m > 0 && tid < n) {
-            const u32x4 bs0 = *reinterpret_cast<const u32x4 *>(&blkstate[0]);
-            const u32x4 bs1 = *reinterpret_cast<const u32x4 *>(&blkstate[4]);
-            const u32x4 bs2 = *reinterpret_cast<const u32x4 *>(&blkstate[8]);
-            const u32x4 bs3 = *reinterpret_cast<const u32x4 *>(&blkstate[12]);
-            const u32x4 pi0 = *reinterpret_cast<const u32x4 *>(&pivinfo[0]);
-            const u32x4 pi1 = *reinterpret_cast<const u32x4 *>(&pivinfo[4]);
-            const uint32_t us[8] = {bs0.x, bs0.y, bs0.z, bs0.w, bs1.x, bs1.y, bs1.z, bs1.w};
-            const uint32_t ps[8] = {bs2.x, bs2.y, bs2.z, bs2.w, bs3.x, bs3.y, bs3.z, bs3.w};
-            const uint32_t pr[8] = {pi0.x, pi0.y, pi0.z, pi0.w, pi1.x, pi1.y, pi1.z, pi1.w};
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if ((sl >> k) & 1u) tau ^= us[k];
-            int j = -1;
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj)
-                if (jj < m && pr[jj] == (uint32_t)tid) j = jj;
-            if (j >= 0) {
+            tau = ttab[sl & 15u] ^ ttab[16 + (sl >> 4)];
+            const uint32_t mk = pivmark[tid];
+            if ((int)(mk >> 3) == blkno) {
+                const int j = (int)(mk & 7u);
                 used = true;
                 myk = r + j;
-#pragma unroll
-                for (int jj = 0; jj < 8; ++jj)
-                    if (jj == j) tau = ps[jj];
+                tau = blkstate[8 + j];
 #pragma unroll
                 for (int w = 0; w < WMAX; ++w) prow[j * WMAX + w] = row[w];
             }
@@ -406,9 +418,10 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
             for (int w = 0; w < WMAX; ++w) tv[w] = ((wm >> w) & 1u) ? mat[w * 256 + tau] : 0ull;
 #pragma unroll
             for (int w = 0; w < WMAX; ++w) row[w] ^= tv[w];
+            if ((wm >> cw) & 1u) cur ^= mat[cw * 256 + tau];
         }
-        // The next block's first write to planes, sl8, the block state or
-        // the table comes after at least one more barrier.
+        // The next block's first write to sl8, the block state or the table
+        // comes after at least one more barrier.
     }
     __syncthreads();
     if (used)
