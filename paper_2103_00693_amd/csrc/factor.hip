@@ -9,8 +9,8 @@
 //   * factor_workgroup_kernel: one workgroup per instance for n <= 1024, one
 //     row per thread in VGPRs, Gauss-Jordan in blocks of 8 columns: the
 //     pivot search runs on bit-planes of the rows' 8-bit slices in one wave,
-//     then every row applies its block update with one lookup in a table of
-//     XOR combinations of the block's pivot rows (LDS).
+//     then every row applies its block update with two lookups per word in
+//     tables of XOR combinations of the block's pivot rows (LDS).
 // Both variants produce the canonical record defined in hlf.h (the RREF is
 // unique, so the pivot rows chosen do not matter).
 #include "factor_wave.h"
@@ -249,9 +249,9 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
     // and lanes 8-15 the pivots' own states; a pivot's state is the XOR of
     // the unit states over its starting slice (a DPP reduction).  The block
     // ends with every row's tag; the current value of every row is then its
-    // start-of-block value plus the XOR of the pivot rows in its tag, so one
-    // lookup in the table T[tau] (2^m entries for m pivots) updates every
-    // row, pivot rows included.
+    // start-of-block value plus the XOR of the pivot rows in its tag, so two
+    // lookups per word in 16-entry tables (one per half of the tag) update
+    // every row, pivot rows included.
     int r = 0, nfree = 0;
     bool used = false;
     int myk = -1;
@@ -380,45 +380,41 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
         r += m;
         if (m == 0) continue;
         __syncthreads();
-        // T[e] word w at mat[w*256 + e]; thread (w, g) fills e = 4g .. 4g+3.
+        // Two tables per word w of the block's pivot rows (as they stood when
+        // the block began): L[e] = XOR of pivot rows j < 4 with bit j of e
+        // set at mat[w*32 + e], H[e] the same for pivot rows 4 + j at
+        // mat[w*32 + 16 + e]; word w of a row's update is L[tau & 15] ^
+        // H[tau >> 4].  Thread (w, e) = (tid / 32, tid % 32) fills one entry.
         // Words that are zero in every pivot row (all words left of the
         // block's word, since a row that is not yet a pivot is zero in every
-        // column already eliminated or found free) are skipped here and in
-        // the lookup; wmask records the others.
+        // column already eliminated or found free) are skipped in the lookup;
+        // wmask records the others, one ballot per wave for its two words.
         {
-            const int w = tid >> 6, g = tid & 63;
-            uint64_t pr[8];
-            uint64_t nz = 0;
+            const int w = tid >> 5, e = tid & 31;
+            const int half = e >> 4, idx = e & 15;
+            uint64_t v = 0;
             if (w < W) {
 #pragma unroll
-                for (int l = 0; l < 8; ++l) {
-                    pr[l] = prow[l * WMAX + w];
-                    if (l < m) nz |= pr[l];
-                }
-                if (g == 0 && nz) atomicOr(&wmask, 1u << w);
+                for (int k = 0; k < 4; ++k)
+                    if (4 * half + k < m && ((idx >> k) & 1)) v ^= prow[(4 * half + k) * WMAX + w];
+                mat[w * 32 + e] = v;
             }
-            if (w < W && nz && 4 * g < (1 << m)) {
-                uint64_t base = 0;
-#pragma unroll
-                for (int l = 2; l < 8; ++l)
-                    if (l < m && ((g >> (l - 2)) & 1)) base ^= pr[l];
-                const uint64_t p1 = (m > 1) ? pr[1] : 0ull;
-                uint64_t *te = &mat[w * 256 + 4 * g];
-                te[0] = base;
-                te[1] = base ^ pr[0];
-                te[2] = base ^ p1;
-                te[3] = base ^ pr[0] ^ p1;
-            }
+            const uint64_t nzb = __ballot(v != 0ull);
+            if (lane == 0 && nzb)
+                atomicOr(&wmask, ((uint32_t)nzb ? 1u << (2 * wave) : 0u) |
+                                     ((uint32_t)(nzb >> 32) ? 1u << (2 * wave + 1) : 0u));
         }
         __syncthreads();
         const uint32_t wm = (uint32_t)__builtin_amdgcn_readfirstlane((int)wmask);
         if (tau) {
+            const uint32_t tl = tau & 15u, th = 16u + (tau >> 4);
             uint64_t tv[WMAX];
 #pragma unroll
-            for (int w = 0; w < WMAX; ++w) tv[w] = ((wm >> w) & 1u) ? mat[w * 256 + tau] : 0ull;
+            for (int w = 0; w < WMAX; ++w)
+                tv[w] = ((wm >> w) & 1u) ? (mat[w * 32 + tl] ^ mat[w * 32 + th]) : 0ull;
 #pragma unroll
             for (int w = 0; w < WMAX; ++w) row[w] ^= tv[w];
-            if ((wm >> cw) & 1u) cur ^= mat[cw * 256 + tau];
+            if ((wm >> cw) & 1u) cur ^= mat[cw * 32 + tl] ^ mat[cw * 32 + th];
         }
         // The next block's first write to sl8, the block state or the table
         // comes after at least one more barrier.
