@@ -39,15 +39,12 @@ namespace {
 __device__ __forceinline__ uint32_t gather4(uint32_t x) { return (x * 0x10204080u) >> 28; }
 
 // Symmetry of one pair of 64x64 tiles: lane l holds x = word J of row 64I+l
-// and y = word I of row 64J+l.  Column b of tile (I, J) is the ballot of bit
-// b of x; it must equal y in lane b (row 64J+b restricted to columns
-// 64I..64I+63).  Returns true, wave-uniform, if some A[64I+l][64J+b] !=
-// A[64J+b][64I+l].  Needs all lanes active.
+// and y = word I of row 64J+l.  Column b of tile (I, J), which lane b of the
+// transposed tile holds, must equal y in lane b (row 64J+b restricted to
+// columns 64I..64I+63).  Returns true, wave-uniform, if some
+// A[64I+l][64J+b] != A[64J+b][64I+l].  Needs all lanes active.
 __device__ __forceinline__ bool tile_pair_asym(uint64_t x, uint64_t y) {
-    uint64_t diff = 0;
-#pragma unroll 8
-    for (int b = 0; b < 64; ++b) diff |= __ballot((x >> b) & 1ull) ^ readlane64(y, b);
-    return diff != 0;
+    return __ballot(wave_transpose64(x) != y) != 0;
 }
 
 template <int WMAX>

@@ -93,8 +93,9 @@ __device__ int factor_wave_core(int n, int W, bool bad_input, const FactorOut &o
         rk[s] = -1;
     }
 
-    // Validation: pad bits zero, A = A^T (the ballot of bit c over slot s is
-    // word s of column c, which must equal word s of row c).
+    // Validation: pad bits zero, A = A^T (slot s of word cw, transposed across
+    // the wave, gives lane l word s of column 64cw + l, which must equal word
+    // s of row 64cw + l).
     bool bad = bad_input;
     const uint64_t lm = last_word_mask(n);
 #pragma unroll
@@ -105,15 +106,12 @@ __device__ int factor_wave_core(int n, int W, bool bad_input, const FactorOut &o
 #pragma unroll
     for (int cw = 0; cw < WMAX; ++cw) {
         if (cw >= W) break;
-        for (int cb = 0; cb < 64; ++cb) {
-            const int c = 64 * cw + cb;
-            if (c >= n) break;
+        const int c = 64 * cw + lane;
 #pragma unroll
-            for (int s = 0; s < WMAX; ++s) {
-                if (s >= W) break;
-                const uint64_t col = __ballot((row[s][cw] >> cb) & 1ull);
-                if (col != sm.orig[c * W + s]) bad = true;
-            }
+        for (int s = 0; s < WMAX; ++s) {
+            if (s >= W) break;
+            const uint64_t col = wave_transpose64(row[s][cw]);
+            if (c < n && col != sm.orig[c * W + s]) bad = true;
         }
     }
     if (__ballot(bad)) {

@@ -73,6 +73,27 @@ __device__ __forceinline__ uint64_t wave_xor_u64(uint64_t v) {
     return v;
 }
 
+// 64x64 bit transpose across one wavefront: lane l holds row l (bit c =
+// column c) and gets column l (bit r = row r).  Step j swaps, between lanes l
+// and l ^ j, the bits whose row and column indices differ in bit j, so after
+// the six steps bit (r, c) sits at (r ^ d, c ^ d), d = r ^ c, i.e. at (c, r).
+// Needs all lanes active.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+#pragma unroll
+    for (int j = 32; j >= 1; j >>= 1) {
+        const uint64_t m = j == 32 ? 0x00000000FFFFFFFFull
+                         : j == 16 ? 0x0000FFFF0000FFFFull
+                         : j == 8  ? 0x00FF00FF00FF00FFull
+                         : j == 4  ? 0x0F0F0F0F0F0F0F0Full
+                         : j == 2  ? 0x3333333333333333ull
+                                   : 0x5555555555555555ull;
+        const uint64_t y = __shfl_xor(x, j, kWave);
+        x = (lane & j) ? ((x & ~m) | ((y & ~m) >> j)) : ((x & m) | ((y & m) << j));
+    }
+    return x;
+}
+
 // Orders the LDS accesses of one wavefront around this point (waits for its
 // outstanding LDS operations; no other wave is involved).  Used by code that
 // runs on a single wave of a larger workgroup.

@@ -109,19 +109,12 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
     const bool has1 = w0 + 1 < W;
     // Transpose: BT[j * 16 + kb] bit t = bit j (of this group's 128 columns)
     // of B_{64kb+t}.  A wave takes one (kb, word) tile: lane t holds the word
-    // of row 64kb+t, the ballot of bit b is column b over the 64 rows, and
-    // lane b keeps it.
+    // of row 64kb+t, and after the transpose lane b holds column b.
     for (int t = wave; t < 2 * KB; t += kMfmaWaves) {
         const int kb = t >> 1, q = t & 1;
         const int k = 64 * kb + lane;
         const uint64_t x = (k < r && (q == 0 || has1)) ? f.basis[(size_t)k * W + w0 + q] : 0ull;
-        uint64_t mine = 0;
-#pragma unroll 8
-        for (int bb = 0; bb < 64; ++bb) {
-            const uint64_t col = __ballot((x >> bb) & 1ull);
-            if (lane == bb) mine = col;
-        }
-        BT[(64 * q + lane) * 16 + kb] = mine;
+        BT[(64 * q + lane) * 16 + kb] = wave_transpose64(x);
     }
     __syncthreads();
     // B operand of chunk (kc, jc): lane (h, n), dword d, byte t holds bit
