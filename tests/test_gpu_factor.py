@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import torch
 
-from hlf_inputs import CONFIG2_SEEDS, CONFIG3_SEEDS, grid_instance, paper_diagonal, random_symmetric
+from hlf_inputs import CONFIG2_SEEDS, CONFIG3_SEEDS, grid_instance, low_rank_symmetric, paper_diagonal, random_symmetric
 from oracle import hlf_oracle as O
 from paper_2103_00693_amd import hlf
 
@@ -61,6 +61,12 @@ def large_cases():
         ("random n=1024", random_symmetric(1024, 3, 0.5)),
         ("zero n=1024", np.zeros((1024, 1024), dtype=np.uint8)),
         ("embedded n=700", _embedded(700, 300, 12)),
+        # most 8-column blocks find no pivot; the row's current word must
+        # still follow every table update
+        ("low rank n=1024 k=20", low_rank_symmetric(1024, 20, 5)),
+        # partial last word and partial last block
+        ("random n=1023", random_symmetric(1023, 21, 0.5)),
+        ("sparse n=1017", random_symmetric(1017, 22, 0.01)),
     ]
 
 
