@@ -267,6 +267,23 @@ def test_batch_solve_one_launch(word_bits):
         assert np.array_equal(narrow_to_u64(outs2[s]), C.enumerate_range(F, 0, counts2[s])[:, 0]), s
 
 
+def test_batch_solve_single_tiny_instance_u16():
+    # the one-launch form of the N=4 workload: a batch of one n = 16 instance
+    A0 = grid_instance(4, seed=0)
+    F = O.factor(A0)
+    total = 1 << F["rank"]
+    B = hlf.Batch([16])
+    A = B.dense_input([A0])
+    out = torch.full((total,), -1, dtype=torch.int16, device="cuda")
+    for rep in range(3):
+        print(f"[batch] solve u16 single rep={rep}", flush=True)
+        B.solve(A, [0], [0], [total], [out], 16)
+        torch.cuda.synchronize()
+        assert B.statuses()[0] == hlf.HLF_OK
+        assert np.array_equal(narrow_to_u64(out), C.enumerate_range(F, 0, total)[:, 0]), rep
+    check_record(B.records()[0], F, "solve u16 record")
+
+
 def test_batch_solve_partial_ranges_and_errors():
     mats = [grid_instance(4, seed=0), grid_instance(5, seed=2), grid_instance(3, p=0.5, seed=4)]
     Fs = [O.factor(m) for m in mats]
