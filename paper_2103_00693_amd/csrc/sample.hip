@@ -78,8 +78,10 @@ __global__ __launch_bounds__(SampleShape<WMAX>::kThreads) void sample_kernel(
 // h = l / 32 (B uses the same assignment; the sum over k does not depend on
 // it): if y holds the chunk's 32 bits, dword d is (y >> (d + 4h)) &
 // 0x01010101, a shift and a mask for A and B alike, and lane l covers sample
-// row l % 32.  Accumulator register i of lane l holds row 8*(i/4) +
-// 4*(l/32) + i%4, column l % 32; bit 0 of each is gathered with ballots.
+// row l % 32.  The product is taken as Z^T = Bm^T * C^T (the basis operand
+// first), so accumulator register i of lane l holds output bit 8*(i/4) +
+// 4*(l/32) + i%4 of the column chunk for sample l % 32: a lane assembles 16
+// bits of its sample's word and takes the other 16 from lane l ^ 32.
 // ---------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
@@ -134,8 +136,6 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
     const int R64 = (r + 63) >> 6;
     const uint64_t lastmask = (r & 63) ? ((1ull << (r & 63)) - 1ull) : ~0ull;
     const int h = lane >> 5, m = lane & 31;
-    // Lane t < 32 collects sample row t: accumulator register it, half ht.
-    const int it = 4 * (m >> 3) + (m & 3), ht = (m >> 2) & 1;
     const uint64_t pass = 32ull * kMfmaWaves;
     for (uint64_t s0 = (uint64_t)blockIdx.y * pass; s0 < num; s0 += (uint64_t)gridDim.y * pass) {
         const uint64_t s = s0 + 32ull * wave + (uint64_t)m;  // this lane's A row
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
             }
 #pragma unroll
             for (int jc = 0; jc < kMfmaJC; ++jc)
-                acc[jc] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0[jc], acc[jc], 0, 0, 0);
+                acc[jc] = __builtin_amdgcn_mfma_i32_32x32x32_i8(b0[jc], a0, acc[jc], 0, 0, 0);
             if (!two) break;
             if (kc + 2 < KC) {
                 if (((kc + 2) & 3) == 0) words_for((kc + 2) >> 2, cw);
@@ -192,19 +192,17 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
             }
 #pragma unroll
             for (int jc = 0; jc < kMfmaJC; ++jc)
-                acc[jc] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1[jc], acc[jc], 0, 0, 0);
+                acc[jc] = __builtin_amdgcn_mfma_i32_32x32x32_i8(b1[jc], a1, acc[jc], 0, 0, 0);
         }
         uint32_t word[kMfmaJC];
 #pragma unroll
         for (int jc = 0; jc < kMfmaJC; ++jc) {
             uint32_t mine = 0;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const uint64_t bm = __ballot(acc[jc][i] & 1);
-                const uint32_t v = ht ? (uint32_t)(bm >> 32) : (uint32_t)bm;
-                if (i == it) mine = v;
-            }
-            word[jc] = mine;
+            for (int i = 0; i < 16; ++i)
+                mine |= ((uint32_t)acc[jc][i] & 1u) << (8 * (i >> 2) + (i & 3));
+            mine <<= 4 * h;
+            word[jc] = mine | (uint32_t)__shfl_xor((int)mine, 32);
         }
         const uint64_t so = s0 + 32ull * wave + (uint64_t)lane;  // row `lane` for lanes < 32
         if (lane < 32 && so < num) {
