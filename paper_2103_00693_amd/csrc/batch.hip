@@ -528,7 +528,10 @@ hlf_status hlf_batch_create(int32_t count, const int32_t *n_host, hlf_batch *out
     for (int i = 0; i < count; ++i)
         if (n_host[i] < 1 || n_host[i] > HLF_MAX_N) return HLF_EINVAL;
     hlf_batch_s *b = new hlf_batch_s();
-    hipGetDevice(&b->device);
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        return HLF_EDEVICE;
+    }
     b->count = count;
     b->n.assign(n_host, n_host + count);
     b->dense_off.resize(count);
@@ -606,10 +609,11 @@ hlf_status hlf_batch_create(int32_t count, const int32_t *n_host, hlf_batch *out
 
 hlf_status hlf_batch_destroy(hlf_batch b) {
     if (!b) return HLF_OK;
-    hipDeviceSynchronize();
-    if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    for (void *p : b->allocations) hipFree(p);
+    // Best-effort teardown: the handle is gone whatever these return.
+    (void)hipDeviceSynchronize();
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (void *p : b->allocations) (void)hipFree(p);
     delete b;
     return HLF_OK;
 }
@@ -858,7 +862,11 @@ hlf_status hlf_batch_tune(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,
         }
     }
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return HLF_EDEVICE;
+    if (hipEventCreate(&e0) != hipSuccess) return HLF_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return HLF_EDEVICE;
+    }
     const int chunks[] = {14, 16, 18, 20, 22};
     const int waves[] = {2, 4, 8, 12};
     hlf_batch_params bestp = b->tuned;
@@ -871,12 +879,12 @@ hlf_status hlf_batch_tune(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,
             if (st != HLF_OK) break;
             float tsum = 0;
             for (int rep = 0; rep < 2 && st == HLF_OK; ++rep) {
-                hipEventRecord(e0, stream);
-                st = batch_reduce_impl(b, A_dev, max_rank, p, stream);
-                hipEventRecord(e1, stream);
-                if (hipEventSynchronize(e1) != hipSuccess) st = HLF_EDEVICE;
+                if (hipEventRecord(e0, stream) != hipSuccess) st = HLF_EDEVICE;
+                if (st == HLF_OK) st = batch_reduce_impl(b, A_dev, max_rank, p, stream);
+                if (st == HLF_OK && hipEventRecord(e1, stream) != hipSuccess) st = HLF_EDEVICE;
+                if (st == HLF_OK && hipEventSynchronize(e1) != hipSuccess) st = HLF_EDEVICE;
                 float ms = 0;
-                hipEventElapsedTime(&ms, e0, e1);
+                if (st == HLF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = HLF_EDEVICE;
                 tsum += ms;
             }
             if (st != HLF_OK) break;
@@ -887,8 +895,8 @@ hlf_status hlf_batch_tune(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,
         }
         if (st != HLF_OK) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != HLF_OK) return st;
     b->tuned = bestp;
     b->has_tuned = true;
@@ -919,13 +927,13 @@ hlf_status hlf_batch_graph_capture(hlf_batch b, const uint8_t *A_dev, int32_t ma
     hipGraphExec_t exec = nullptr;
     if (st == HLF_OK && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess)
         st = HLF_EDEVICE;
-    hipStreamDestroy(s);
+    (void)hipStreamDestroy(s);
     if (st != HLF_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return st;
     }
-    if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->graph = g;
     b->graph_exec = exec;
     return HLF_OK;

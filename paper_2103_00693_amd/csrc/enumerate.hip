@@ -437,24 +437,23 @@ __global__ __launch_bounds__(256) void reduce_general_kernel(FactorIn f, uint64_
 #pragma unroll
             for (int w = 0; w < WMAX; ++w) xacc[w] ^= z[w];
         }
+        // Lane b counts bit 64w + b over the wave's valid solutions: bit b of
+        // z[w] across the lanes is lane b's word after the wave transpose.
+        const uint64_t vm = __ballot(valid);
 #pragma unroll
-        for (int w = 0; w < WMAX; ++w) {
-            if (w >= W) break;
-            for (int b = 0; b < 64; ++b) {
-                const uint64_t m = __ballot(valid && ((z[w] >> b) & 1ull));
-                if (lane == b) pc[w] += (uint64_t)__builtin_popcountll(m);
-            }
-        }
+        for (int w = 0; w < WMAX; ++w)
+            if (w < W) pc[w] += (uint64_t)__builtin_popcountll(wave_transpose64(z[w]) & vm);
     }
     const uint64_t wsum = wave_sum_u64(acc);
     if (lane == 0 && wsum) atomicAdd((unsigned long long *)hash, (unsigned long long)wsum);
 #pragma unroll
     for (int w = 0; w < WMAX; ++w) {
-        if (w >= W) break;
-        const uint64_t wx = wave_xor_u64(xacc[w]);
-        if (xorfold && lane == 0 && wx) atomicXor((unsigned long long *)&xorfold[w], (unsigned long long)wx);
-        const int bit = 64 * w + lane;
-        if (bit < n && pc[w]) atomicAdd(&part[bit], (unsigned long long)pc[w]);
+        if (w < W) {
+            const uint64_t wx = wave_xor_u64(xacc[w]);
+            if (xorfold && lane == 0 && wx) atomicXor((unsigned long long *)&xorfold[w], (unsigned long long)wx);
+            const int bit = 64 * w + lane;
+            if (bit < n && pc[w]) atomicAdd(&part[bit], (unsigned long long)pc[w]);
+        }
     }
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += blockDim.x)

@@ -173,7 +173,6 @@ __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *
     __shared__ uint16_t pivmark[64 * WMAX];  // block * 8 + j for the block's j-th pivot row
     __shared__ uint32_t ttab[32];            // tag of a slice: ttab[low nibble] ^ ttab[16 + high]
     __shared__ __align__(16) uint32_t blkstate[16];
-    __shared__ __align__(16) int pivinfo[8];
     __shared__ int blk[2];
     __shared__ uint32_t wmask;
     __shared__ unsigned long long shiftw[WMAX];

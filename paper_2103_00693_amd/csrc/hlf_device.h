@@ -81,7 +81,8 @@ __device__ __forceinline__ uint64_t wave_xor_u64(uint64_t v) {
 __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
     const int lane = (int)(threadIdx.x & (kWave - 1));
 #pragma unroll
-    for (int j = 32; j >= 1; j >>= 1) {
+    for (int step = 5; step >= 0; --step) {
+        const int j = 1 << step;
         const uint64_t m = j == 32 ? 0x00000000FFFFFFFFull
                          : j == 16 ? 0x0000FFFF0000FFFFull
                          : j == 8  ? 0x00FF00FF00FF00FFull

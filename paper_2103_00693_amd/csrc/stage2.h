@@ -297,13 +297,13 @@ __device__ WavePartial<WW> wave_reduce_range(const uint64_t *Bx, const uint64_t 
                     }
                     acc += h;
                 }
+                // Lane b counts bit 64w + b over the valid lanes: bit b of z[w]
+                // across the lanes is lane b's word after the wave transpose
+                // (bits at or past n are zero in every solution).
+                const uint64_t vm = __ballot(valid);
 #pragma unroll
-                for (int w = 0; w < WW; ++w) {
-                    for (int b = 0; b < 64 && 64 * w + b < n; ++b) {
-                        const uint64_t m = __ballot(valid && ((z[w] >> b) & 1ull));
-                        if (lane == b) pc[w] += (uint64_t)__builtin_popcountll(m);
-                    }
-                }
+                for (int w = 0; w < WW; ++w)
+                    pc[w] += (uint64_t)__builtin_popcountll(wave_transpose64(z[w]) & vm);
             }
         }
 #pragma unroll
