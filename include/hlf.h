@@ -92,7 +92,8 @@ typedef enum hlf_status {
 #define HLF_ACCUMULATE 1u       /* add into counts/hash/xorfold instead of overwriting */
 
 /* Flags of hlf_factor_ex. */
-#define HLF_FACTOR_WORKGROUP 1u /* force the workgroup (LDS) variant for any n   */
+#define HLF_FACTOR_WORKGROUP 1u   /* force the workgroup (LDS) variant for any n   */
+#define HLF_FACTOR_PACK_STATUS 2u /* f->status holds the hlf_pack_dense verdict    */
 
 /* Flags of hlf_enumerate_ex. */
 #define HLF_ORDER_COUNTER 1u    /* binary-counter order (Section 4) instead of Gray */
@@ -142,8 +143,13 @@ hlf_status hlf_pack_dense(const uint8_t *A_dev, int32_t n, uint64_t *rows_dev,
  * Returns HLF_EINVAL for NULL pointers, n out of range or words != ceil(n/64). */
 hlf_status hlf_factor(const uint64_t *rows_dev, const hlf_factors *f, hipStream_t stream);
 
-/* hlf_factor with flags (HLF_FACTOR_WORKGROUP selects the workgroup variant
- * for every n; the results are identical).                                     */
+/* hlf_factor with flags.  HLF_FACTOR_WORKGROUP selects the workgroup variant
+ * for every n (the results are identical).  HLF_FACTOR_PACK_STATUS: the caller
+ * passed f->status as the status_dev of an hlf_pack_dense of these rows
+ * enqueued earlier on the same stream; if that verdict is not HLF_OK it stays
+ * in f->status and nothing else of the record is written (the packed rows of
+ * an invalid matrix are not factored), else the call behaves as without the
+ * flag.  This saves merging the two verdicts after the call.                   */
 hlf_status hlf_factor_ex(const uint64_t *rows_dev, const hlf_factors *f, uint32_t flags,
                          hipStream_t stream);
 

@@ -665,7 +665,7 @@ hlf_status hlf_batch_factor_dense(hlf_batch b, const uint8_t *A_dev, hipStream_t
         out.kernel = b->kernel + b->mat_off[i];
         hlf_status s = hlf::launch_pack(A_dev + b->dense_off[i], n, W, b->rows, b->pack_status, stream);
         if (s != HLF_OK) return s;
-        s = hlf::launch_factor(b->rows, n, W, out, false, stream);
+        s = hlf::launch_factor(b->rows, n, W, out, false, false, stream);
         if (s != HLF_OK) return s;
         hipLaunchKernelGGL(hlf::merge_pack_status_kernel, dim3(1), dim3(64), 0, stream, out.status,
                            b->pack_status);

@@ -136,9 +136,12 @@ __global__ __launch_bounds__(64 * WMAX) void pack_dense_kernel(const uint8_t *__
     if (tid == 0) *status = bad ? HLF_ENOTSYM : HLF_OK;
 }
 
+// keep_bad: out.status already holds the pack verdict for these rows; a
+// verdict other than HLF_OK stays and nothing else is written.
 template <int WMAX>
 __global__ __launch_bounds__(64) void factor_wave_kernel(const uint64_t *__restrict__ rows, int n,
-                                                         int W, FactorOut out) {
+                                                         int W, FactorOut out, int keep_bad) {
+    if (keep_bad && *(volatile int32_t *)out.status != HLF_OK) return;
     __shared__ WaveSmem<WMAX> sm;
     wave_load_rows<WMAX>(rows, n, W, sm);
     factor_wave_core<WMAX>(n, W, false, out, sm);
@@ -161,7 +164,9 @@ __device__ __forceinline__ int lower_bound_int(const int *a, int len, int key) {
 
 template <int WMAX>
 __global__ __launch_bounds__(1024) void factor_workgroup_kernel(const uint64_t *__restrict__ rows,
-                                                                int n, int W, FactorOut out) {
+                                                                int n, int W, FactorOut out,
+                                                                int keep_bad) {
+    if (keep_bad && *(volatile int32_t *)out.status != HLF_OK) return;
     constexpr int NP = 64 * WMAX;
     constexpr int kMatWords = 64 * WMAX * WMAX > 256 * WMAX ? 64 * WMAX * WMAX : 256 * WMAX;
     __shared__ uint64_t mat[kMatWords];
@@ -492,17 +497,18 @@ hlf_status launch_pack_t(const uint8_t *A, int n, int W, uint64_t *rows, int32_t
 }
 
 template <int WMAX>
-hlf_status launch_wave_t(const uint64_t *rows, int n, int W, const FactorOut &out,
+hlf_status launch_wave_t(const uint64_t *rows, int n, int W, const FactorOut &out, int keep_bad,
                          hipStream_t stream) {
-    hipLaunchKernelGGL(factor_wave_kernel<WMAX>, dim3(1), dim3(64), 0, stream, rows, n, W, out);
+    hipLaunchKernelGGL(factor_wave_kernel<WMAX>, dim3(1), dim3(64), 0, stream, rows, n, W, out,
+                       keep_bad);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
 }
 
 template <int WMAX>
 hlf_status launch_workgroup_t(const uint64_t *rows, int n, int W, const FactorOut &out,
-                              hipStream_t stream) {
+                              int keep_bad, hipStream_t stream) {
     hipLaunchKernelGGL(factor_workgroup_kernel<WMAX>, dim3(1), dim3(64 * W), 0, stream, rows, n,
-                       W, out);
+                       W, out, keep_bad);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
 }
 
@@ -519,15 +525,16 @@ hlf_status launch_pack(const uint8_t *A, int n, int W, uint64_t *rows, int32_t *
 }
 
 hlf_status launch_factor(const uint64_t *rows, int n, int W, const FactorOut &out,
-                         bool force_workgroup, hipStream_t stream) {
+                         bool force_workgroup, bool keep_pack_status, hipStream_t stream) {
+    const int kb = keep_pack_status ? 1 : 0;
     // One wave is faster up to n = 64; from two words on, the blocked
     // workgroup elimination is.
-    if (!force_workgroup && W == 1) return launch_wave_t<1>(rows, n, W, out, stream);
-    if (W <= 1) return launch_workgroup_t<1>(rows, n, W, out, stream);
-    if (W <= 2) return launch_workgroup_t<2>(rows, n, W, out, stream);
-    if (W <= 4) return launch_workgroup_t<4>(rows, n, W, out, stream);
-    if (W <= 8) return launch_workgroup_t<8>(rows, n, W, out, stream);
-    return launch_workgroup_t<16>(rows, n, W, out, stream);
+    if (!force_workgroup && W == 1) return launch_wave_t<1>(rows, n, W, out, kb, stream);
+    if (W <= 1) return launch_workgroup_t<1>(rows, n, W, out, kb, stream);
+    if (W <= 2) return launch_workgroup_t<2>(rows, n, W, out, kb, stream);
+    if (W <= 4) return launch_workgroup_t<4>(rows, n, W, out, kb, stream);
+    if (W <= 8) return launch_workgroup_t<8>(rows, n, W, out, kb, stream);
+    return launch_workgroup_t<16>(rows, n, W, out, kb, stream);
 }
 
 }  // namespace hlf

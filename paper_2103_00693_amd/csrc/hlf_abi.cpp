@@ -80,7 +80,7 @@ hlf_status hlf_pack_dense(const uint8_t *A_dev, int32_t n, uint64_t *rows_dev,
 hlf_status hlf_factor_ex(const uint64_t *rows_dev, const hlf_factors *f, uint32_t flags,
                          hipStream_t stream) {
     if (!rows_dev || !record_ok(f)) return HLF_EINVAL;
-    if (flags & ~HLF_FACTOR_WORKGROUP) return HLF_EINVAL;
+    if (flags & ~(HLF_FACTOR_WORKGROUP | HLF_FACTOR_PACK_STATUS)) return HLF_EINVAL;
     hlf::FactorOut out;
     out.status = f->status;
     out.rank = f->rank;
@@ -89,7 +89,7 @@ hlf_status hlf_factor_ex(const uint64_t *rows_dev, const hlf_factors *f, uint32_
     out.shift = f->shift;
     out.kernel = f->kernel;
     return hlf::launch_factor(rows_dev, f->n, f->words, out, (flags & HLF_FACTOR_WORKGROUP) != 0,
-                              stream);
+                              (flags & HLF_FACTOR_PACK_STATUS) != 0, stream);
 }
 
 hlf_status hlf_factor(const uint64_t *rows_dev, const hlf_factors *f, hipStream_t stream) {

@@ -33,7 +33,7 @@ int device_cu_count();
 hlf_status launch_pack(const uint8_t *A, int n, int W, uint64_t *rows, int32_t *status,
                        hipStream_t stream);
 hlf_status launch_factor(const uint64_t *rows, int n, int W, const FactorOut &out,
-                         bool force_workgroup, hipStream_t stream);
+                         bool force_workgroup, bool keep_pack_status, hipStream_t stream);
 hlf_status launch_enumerate(const FactorIn &f, uint64_t begin, uint64_t count, int word_bits,
                             bool counter_order, void *out, hipStream_t stream);
 // Gray order.

@@ -31,6 +31,7 @@ HLF_MAX_ENUM_RANK = 62
 HLF_ORDER_COUNTER = 1
 HLF_ACCUMULATE = 1
 HLF_FACTOR_WORKGROUP = 1
+HLF_FACTOR_PACK_STATUS = 2
 
 EXPORTED = (
     "hlf_version", "hlf_status_string", "hlf_words_for", "hlf_pack_dense", "hlf_factor",
@@ -150,6 +151,36 @@ class Factors:
                            self.pivots.data_ptr(), self.basis.data_ptr(), self.shift.data_ptr(),
                            self.kernel.data_ptr() if kernel else 0)
 
+    @classmethod
+    def packed(cls, n: int, device=None, kernel: bool = False) -> "Factors":
+        """A record in ONE uninitialised device buffer: status and rank
+        adjacent (one 8-byte copy reads both), then pivots, shift, basis and
+        the optional kernel vectors.  hlf_factor writes every field that a
+        later call reads (the basis rows past r are not read)."""
+        if not 1 <= n <= HLF_MAX_N:
+            raise HlfError(HLF_EINVAL, f"n={n} outside [1, {HLF_MAX_N}]")
+        self = cls.__new__(cls)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        W = words_for(n)
+        self.n, self.words, self.device = n, W, dev
+        piv_words = (n + 1) // 2                       # int32 pivots in int64 units
+        total = 1 + piv_words + W + n * W + (n * W if kernel else 0)
+        buf = torch.empty(total, dtype=torch.int64, device=dev)
+        self._buf = buf
+        head = buf[:1].view(torch.int32)               # [status, rank]
+        self.status, self.rank = head[0:1], head[1:2]
+        self.status_rank = head
+        self.pivots = buf[1:1 + piv_words].view(torch.int32)[:n]
+        o = 1 + piv_words
+        self.shift = buf[o:o + W]
+        self.basis = buf[o + W:o + W + n * W].view(n, W)
+        o += W + n * W
+        self.kernel = buf[o:o + n * W].view(n, W) if kernel else None
+        self._c = _Factors(n, W, self.status.data_ptr(), self.rank.data_ptr(),
+                           self.pivots.data_ptr(), self.basis.data_ptr(), self.shift.data_ptr(),
+                           self.kernel.data_ptr() if kernel else 0)
+        return self
+
     @property
     def c(self):
         return ctypes.byref(self._c)
@@ -205,11 +236,13 @@ def pack_dense(A: torch.Tensor, rows: torch.Tensor | None = None,
 
 
 def factor(rows: torch.Tensor, n: int, F: Factors | None = None, workgroup: bool = False,
-           stream=None) -> Factors:
-    """A1-A4: hlf_factor(_ex) of packed rows into a device record."""
+           stream=None, pack_status: bool = False) -> Factors:
+    """A1-A4: hlf_factor(_ex) of packed rows into a device record.  With
+    pack_status, F.status must have been the status output of the
+    pack_dense of these rows on the same stream (HLF_FACTOR_PACK_STATUS)."""
     if F is None:
         F = Factors(n, device=rows.device)
-    flags = HLF_FACTOR_WORKGROUP if workgroup else 0
+    flags = (HLF_FACTOR_WORKGROUP if workgroup else 0) | (HLF_FACTOR_PACK_STATUS if pack_status else 0)
     _check(lib().hlf_factor_ex(_ptr(rows), F.c, flags, _stream(stream)), "hlf_factor")
     return F
 

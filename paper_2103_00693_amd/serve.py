@@ -82,11 +82,7 @@ class _Active:
     n: int
     footprint: int
     admitted: float
-    Ad: torch.Tensor | None = None
-    rows: torch.Tensor | None = None
     F: hlf.Factors | None = None
-    rank_host: torch.Tensor | None = None
-    status_host: torch.Tensor | None = None
     out: torch.Tensor | None = None
     host_out: torch.Tensor | None = None
     event: torch.cuda.Event | None = None
@@ -122,8 +118,15 @@ class Server:
         self.enum_max_rank = enum_max_rank
         self.cache_entries = cache_entries
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
-        # per-slot pinned staging of the dense input (grown on demand)
+        # Per-slot buffers, grown on demand and reused: a slot takes its next
+        # request only after every event of the previous one has fired.
+        # Pinned staging of the dense input, its device copy, the packed rows,
+        # the stage-2 output, and the pinned (status, rank) pair.
         self.staging: list[torch.Tensor | None] = [None] * slots
+        self.dev_A: list[torch.Tensor | None] = [None] * slots
+        self.dev_rows: list[torch.Tensor | None] = [None] * slots
+        self.dev_out: list[torch.Tensor | None] = [None] * slots
+        self.head_host = [torch.empty(2, dtype=torch.int32, pin_memory=True) for _ in range(slots)]
         self.cache: collections.OrderedDict[bytes, _Entry] = collections.OrderedDict()
         self.cache_bytes = 0
         self.in_flight = 0
@@ -159,35 +162,38 @@ class Server:
             a.cache_hit = True
             self.stats["cache_hits"] += 1
             a.F, a.rank, a.status = hit.F, hit.rank, hit.status
-            for t in (a.F.status, a.F.rank, a.F.pivots, a.F.basis, a.F.shift):
-                t.record_stream(s)  # keep the memory until this stream is done with it
+            a.F._buf.record_stream(s)  # keep the memory until this stream is done with it
             self._launch_phase2(a)
             return a
         with torch.cuda.stream(s):
-            # H2D through the slot's pinned staging buffer; the slot is not
-            # reused before this request's events have fired.
-            st = self.staging[slot]
-            if st is None or st.numel() < n * n:
-                st = torch.empty(max(n * n, 1 << 16), dtype=torch.uint8, pin_memory=True)
-                self.staging[slot] = st
+            # H2D through the slot's pinned staging buffer.
+            st = self._grow(self.staging, slot, n * n, torch.uint8, pinned=True)
             st[: n * n].numpy()[:] = A.reshape(-1)
-            a.Ad = torch.empty((n, n), dtype=torch.uint8, device=self.device)
-            a.Ad.view(-1).copy_(st[: n * n], non_blocking=True)
-            a.F = hlf.Factors(n, device=self.device, kernel=False)
-            a.rows = torch.empty((n, hlf.words_for(n)), dtype=torch.int64, device=self.device)
-            pack_status = torch.empty(1, dtype=torch.int32, device=self.device)
-            hlf.pack_dense(a.Ad, a.rows, pack_status, stream=s)
-            hlf.factor(a.rows, n, a.F, stream=s)
-            # a failed pack (entries other than 0/1) overrides the factor's verdict
-            bad = pack_status.ne(hlf.HLF_OK)
-            a.F.status.copy_(torch.where(bad, pack_status, a.F.status))
-            a.rank_host = torch.empty(1, dtype=torch.int32, pin_memory=True)
-            a.status_host = torch.empty(1, dtype=torch.int32, pin_memory=True)
-            a.rank_host.copy_(a.F.rank, non_blocking=True)
-            a.status_host.copy_(a.F.status, non_blocking=True)
+            Ad = self._grow(self.dev_A, slot, n * n, torch.uint8)[: n * n]
+            Ad.copy_(st[: n * n], non_blocking=True)
+            W = hlf.words_for(n)
+            rows = self._grow(self.dev_rows, slot, n * W, torch.int64)[: n * W].view(n, W)
+            # The record outlives the request when it is cached: its own buffer.
+            a.F = hlf.Factors.packed(n, device=self.device)
+            # pack writes its verdict into the record's status; the factor
+            # keeps a failed one (HLF_FACTOR_PACK_STATUS)
+            hlf.pack_dense(Ad.view(n, n), rows, a.F.status, stream=s)
+            hlf.factor(rows, n, a.F, stream=s, pack_status=True)
+            self.head_host[slot].copy_(a.F.status_rank, non_blocking=True)
             a.event = torch.cuda.Event()
             a.event.record(s)
         return a
+
+    def _grow(self, pool, slot: int, numel: int, dtype, pinned: bool = False) -> torch.Tensor:
+        buf = pool[slot]
+        if buf is None or buf.numel() < numel:
+            size = max(numel, 1 << 16)
+            if pinned:
+                buf = torch.empty(size, dtype=dtype, pin_memory=True)
+            else:
+                buf = torch.empty(size, dtype=dtype, device=self.device)
+            pool[slot] = buf
+        return buf
 
     def _launch_phase2(self, a: _Active):
         a.phase = 2
@@ -200,10 +206,17 @@ class Server:
             elif r <= self.enum_max_rank and n <= 64:
                 a.kind = "enumerate"
                 wb = 16 if n <= 16 else 32 if n <= 32 else 64
-                a.out = hlf.enumerate_solutions(a.F, 0, 1 << r, wb, stream=s)
+                dt = {16: torch.int16, 32: torch.int32, 64: torch.int64}[wb]
+                nbytes = (1 << r) * wb // 8
+                out = self._grow(self.dev_out, a.slot, (nbytes + 7) // 8, torch.int64)
+                a.out = out.view(torch.uint8)[:nbytes].view(dt)
+                hlf.enumerate_solutions(a.F, 0, 1 << r, wb, out=a.out, stream=s)
             else:
                 a.kind = "sample"
-                a.out = hlf.sample(a.F, a.req.seed, self.num_samples, stream=s)
+                W = a.F.words
+                out = self._grow(self.dev_out, a.slot, self.num_samples * W, torch.int64)
+                a.out = out[: self.num_samples * W].view(self.num_samples, W)
+                hlf.sample(a.F, a.req.seed, self.num_samples, out=a.out, stream=s)
             if a.out is not None:
                 a.host_out = torch.empty(a.out.shape, dtype=a.out.dtype, pin_memory=True)
                 a.host_out.copy_(a.out, non_blocking=True)
@@ -263,8 +276,8 @@ class Server:
                     continue
                 now = time.perf_counter() - t0
                 if a.phase == 1:
-                    a.rank = int(a.rank_host[0])
-                    a.status = int(a.status_host[0])
+                    head = self.head_host[slot]
+                    a.status, a.rank = int(head[0]), int(head[1])
                     self._launch_phase2(a)
                 else:
                     done.append(self._finish(a, now))

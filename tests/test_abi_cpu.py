@@ -68,7 +68,7 @@ def test_host_detected_errors():
     wrong_w = _rec(100)
     wrong_w.words = 1
     assert L.hlf_factor(ctypes.c_void_p(8), ctypes.byref(wrong_w), None) == hlf.HLF_EINVAL
-    assert L.hlf_factor_ex(ctypes.c_void_p(8), ctypes.byref(good), 2, None) == hlf.HLF_EINVAL
+    assert L.hlf_factor_ex(ctypes.c_void_p(8), ctypes.byref(good), 4, None) == hlf.HLF_EINVAL  # unknown flag bit
     assert L.hlf_pack_dense(None, 4, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == hlf.HLF_EINVAL
     assert L.hlf_pack_dense(ctypes.c_void_p(8), 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == hlf.HLF_EINVAL
     assert L.hlf_pack_dense(ctypes.c_void_p(8), 1025, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == hlf.HLF_EINVAL

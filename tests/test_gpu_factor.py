@@ -166,3 +166,29 @@ def test_factor_agrees_with_words_of_basis_layout():
     rows = oracle_rows(A)
     for k, p in enumerate(got["pivots"][:got["rank"]]):
         assert got["basis"][k] == words_to_ints(rows[p:p + 1])[0]
+
+
+@pytest.mark.parametrize("n", [16, 100, 1024])
+def test_factor_keeps_pack_verdict_in_packed_record(n):
+    # HLF_FACTOR_PACK_STATUS: pack writes its verdict into the record's
+    # status; a failed one stays and the record is not otherwise written.
+    F = hlf.Factors.packed(n, kernel=True)
+    W = hlf.words_for(n)
+    rows = torch.empty((n, W), dtype=torch.int64, device="cuda")
+    bad = random_symmetric(n, 60 + n, 0.5)
+    bad[1 % n, 2 % n] = bad[2 % n, 1 % n] = 2  # not a 0/1 matrix
+    print(f"[factor] pack verdict kept n={n}", flush=True)
+    hlf.pack_dense(device_matrix(bad), rows, F.status)
+    F.rank.fill_(-7)
+    hlf.factor(rows, n, F, pack_status=True)
+    torch.cuda.synchronize()
+    assert int(F.status.item()) == hlf.HLF_ENOTSYM
+    assert int(F.rank.item()) == -7
+    # a valid matrix through the same record and flag: the plain result
+    good = random_symmetric(n, 70 + n, 0.5)
+    hlf.pack_dense(device_matrix(good), rows, F.status)
+    hlf.factor(rows, n, F, pack_status=True)
+    torch.cuda.synchronize()
+    ref = O.factor(good)
+    assert_record_matches(F, ref, f"packed record n={n}")
+    assert F.status_rank.cpu().tolist() == [hlf.HLF_OK, ref["rank"]]
