@@ -169,12 +169,13 @@ __device__ void enum_tiles_w1(const uint64_t *Bx, uint64_t l, uint64_t begin, ui
     const int tid = threadIdx.x;
     // Lane constants l ^ F(tid*V + e).  F is linear in the bits of the index,
     // so F(tid*V + e) = F(tid << LOGV) ^ F(e): about LOGV + 10 lookups instead
-    // of V * S.  A launch that fits on the device at once (its start-up is
-    // its latency) takes the short form; large launches keep the per-index
-    // form, whose longer start-up spreads the workgroups' first stores and
-    // measured about 1% faster on them.
+    // of V * S.  The workgroups that start with the launch (all of a launch
+    // that fits on the device at once) take the short form: their start-up
+    // is the launch's ramp.  The later ones keep the per-index form, whose
+    // longer start-up spreads their first stores (measured about 1% faster
+    // than the short form everywhere).
     uint64_t lo[V];
-    if (gridDim.x <= kShortSeedGrid) {
+    if (gridDim.x <= kShortSeedGrid || blockIdx.x < kShortSeedGrid) {
         uint64_t base = l;
 #pragma unroll
         for (int j = 0; j < kLogTileThreads; ++j)
