@@ -414,8 +414,10 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                                   "the multi-GPU sharding is described in DESIGN.md"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; across GPUs the "
+                                   "index range [0, 2^r) would split into contiguous slices, "
+                                   "materialised with no communication and reduced with one "
+                                   "all-reduce"}))
         sys.exit(2)
 
     import numpy as np
