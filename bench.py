@@ -145,20 +145,19 @@ def tiny_mode(hlf, torch, stream, dev):
             ms.append(e0.elapsed_time(e1))
     F.check()
     med = sorted(ms)[len(ms) // 2]
-    # The same work as ONE launch: hlf_batch_solve on a batch of this one
-    # instance (validate + factor on the first workgroup, materialise on all).
-    B = hlf.Batch([16])
-    Ad = B.dense_input([grid_instance(4, seed=0)], device=dev)
+    # The same work as ONE launch: hlf_solve_dense (every workgroup packs and
+    # factors the instance, then materialises its own tiles).
+    F1 = hlf.Factors(16, device=dev)
     out1 = torch.empty(1 << r, dtype=torch.int16, device=dev)
     fused = []
     for k in range(reps + 5):
         e0.record(stream)
-        B.solve(Ad, [0], [0], [1 << r], [out1], 16, stream=stream)
+        hlf.solve_dense(A, F1, 0, 1 << r, 16, out=out1, stream=stream)
         e1.record(stream)
         stream.synchronize()
         if k >= 5:
             fused.append(e0.elapsed_time(e1))
-    if not torch.equal(out1, out) or B.statuses()[0] != hlf.HLF_OK:
+    if not torch.equal(out1, out) or int(F1.status.item()) != hlf.HLF_OK:
         raise RuntimeError("one-launch solve differs from the launch chain")
     fmed = sorted(fused)[len(fused) // 2]
     return {"workload": "N=4 grid (n=16), all edges, seed 0: pack + factor + materialise 2^r uint16",
@@ -166,7 +165,7 @@ def tiny_mode(hlf, torch, stream, dev):
             "solutions_per_s_G": round((1 << r) / (med * 1e-3) / 1e9, 3),
             "launches": "pack, factor, enumerate",
             "one_launch_median_us": round(fmed * 1e3, 2),
-            "one_launch": "hlf_batch_solve on a batch of this instance"}
+            "one_launch": "hlf_solve_dense"}
 
 
 def steady_mode(hlf, torch, stream, dev):

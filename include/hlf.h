@@ -153,6 +153,24 @@ hlf_status hlf_factor(const uint64_t *rows_dev, const hlf_factors *f, hipStream_
 hlf_status hlf_factor_ex(const uint64_t *rows_dev, const hlf_factors *f, uint32_t flags,
                          hipStream_t stream);
 
+/* Stages 1 and 2 of one small instance in one launch (Sections 1-2: the
+ * validation of A, tasks (1)-(4) and the traversal of Eq. (3)): the result of
+ * hlf_pack_dense + hlf_factor + hlf_enumerate, for n <= 64.
+ *   A_dev      dev uint8 [n*n], row-major, entries 0 or 1 (as hlf_pack_dense).
+ *   f          record with n <= 64 (words = 1); written as by hlf_factor.
+ *   begin, count, word_bits, out_dev  as hlf_enumerate with a uint16/uint32/
+ *              uint64 word per solution (word_bits 16, 32 or 64, >= n), begin
+ *              a multiple of 16 / (word_bits / 8) and out_dev 16-byte aligned.
+ * Device errors: HLF_ENOTSYM (invalid A) or HLF_ERANGE (r > 62 or begin +
+ * count > 2^r) in f->status, and nothing is written to out_dev.  count = 0
+ * runs stage 1 only.  Every workgroup of the launch factors the instance
+ * itself, so no workgroup waits for another: meant for latency-bound small
+ * counts (for large counts hlf_factor + hlf_enumerate factor once).
+ * Returns HLF_EINVAL for NULL pointers, n > 64, a word size not allowed for n,
+ * or a misaligned begin or out_dev.                                            */
+hlf_status hlf_solve_dense(const uint8_t *A_dev, const hlf_factors *f, uint64_t begin,
+                           uint64_t count, int32_t word_bits, void *out_dev, hipStream_t stream);
+
 /* Stage 2, materialise (Section 2, the traversal of R^(r) through Eq. (3) and
  * the final CNOT layer): out[i - begin] = z_i for i in [begin, begin + count).
  *   word_bits  16, 32 or 64 when n <= word_bits <= 64: one uint16/uint32/uint64

@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhlf.so")
 
-SOURCES = ["factor.hip", "enumerate.hip", "sample.hip", "verify.hip", "batch.hip", "hlf_abi.cpp"]
+SOURCES = ["factor.hip", "enumerate.hip", "sample.hip", "verify.hip", "batch.hip", "solve.hip",
+           "hlf_abi.cpp"]
 
 ARCH = os.environ.get("HLF_OFFLOAD_ARCH", "gfx950")
 

@@ -116,6 +116,25 @@ hlf_status hlf_enumerate_ex(const hlf_factors *f, uint64_t begin, uint64_t count
                                  out_dev, stream);
 }
 
+hlf_status hlf_solve_dense(const uint8_t *A_dev, const hlf_factors *f, uint64_t begin,
+                           uint64_t count, int32_t word_bits, void *out_dev, hipStream_t stream) {
+    if (!A_dev || !record_ok(f)) return HLF_EINVAL;
+    if (f->words != 1) return HLF_EINVAL;  // n <= 64
+    if ((word_bits != 16 && word_bits != 32 && word_bits != 64) || f->n > word_bits)
+        return HLF_EINVAL;
+    const uint64_t V = 16 / (uint64_t)(word_bits / 8);
+    if (count > 0 && (!out_dev || ((uintptr_t)out_dev & 15u) != 0 || begin % V != 0))
+        return HLF_EINVAL;
+    hlf::FactorOut out;
+    out.status = f->status;
+    out.rank = f->rank;
+    out.pivots = f->pivots;
+    out.basis = f->basis;
+    out.shift = f->shift;
+    out.kernel = f->kernel;
+    return hlf::launch_solve_dense(A_dev, f->n, out, begin, count, word_bits, out_dev, stream);
+}
+
 hlf_status hlf_enumerate_circuit(const hlf_factors *f, const uint64_t *rows_dev, int32_t grid_N,
                                  uint64_t begin, uint64_t count, int32_t word_bits, void *out_dev,
                                  hipStream_t stream) {

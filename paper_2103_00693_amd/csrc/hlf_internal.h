@@ -32,6 +32,11 @@ int device_cu_count();
 
 hlf_status launch_pack(const uint8_t *A, int n, int W, uint64_t *rows, int32_t *status,
                        hipStream_t stream);
+// Pack + factor + materialise of one instance with n <= 64 in one launch
+// (word_bits 16/32/64 >= n, begin a multiple of the 16-byte vector, out
+// 16-byte aligned).
+hlf_status launch_solve_dense(const uint8_t *A, int n, const FactorOut &rec, uint64_t begin,
+                              uint64_t count, int word_bits, void *out, hipStream_t stream);
 hlf_status launch_factor(const uint64_t *rows, int n, int W, const FactorOut &out,
                          bool force_workgroup, bool keep_pack_status, hipStream_t stream);
 hlf_status launch_enumerate(const FactorIn &f, uint64_t begin, uint64_t count, int word_bits,

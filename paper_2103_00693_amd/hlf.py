@@ -35,7 +35,7 @@ HLF_FACTOR_PACK_STATUS = 2
 
 EXPORTED = (
     "hlf_version", "hlf_status_string", "hlf_words_for", "hlf_pack_dense", "hlf_factor",
-    "hlf_factor_ex", "hlf_enumerate", "hlf_enumerate_ex", "hlf_enumerate_circuit",
+    "hlf_factor_ex", "hlf_solve_dense", "hlf_enumerate", "hlf_enumerate_ex", "hlf_enumerate_circuit",
     "hlf_enumerate_reduce", "hlf_sample", "hlf_pair_stats", "hlf_membership",
     "hlf_batch_create", "hlf_batch_destroy", "hlf_batch_get_layout", "hlf_batch_factor_dense",
     "hlf_batch_enumerate", "hlf_batch_enumerate_overlap", "hlf_batch_solve", "hlf_batch_reduce", "hlf_batch_tune", "hlf_batch_graph_capture",
@@ -97,6 +97,8 @@ def lib():
         L.hlf_membership.argtypes = [fp, vp, u64, vp, vp]
         L.hlf_enumerate_circuit.restype = i32
         L.hlf_enumerate_circuit.argtypes = [fp, vp, i32, u64, u64, i32, vp, vp]
+        L.hlf_solve_dense.restype = i32
+        L.hlf_solve_dense.argtypes = [vp, fp, u64, u64, i32, vp, vp]
         L.hlf_enumerate_reduce.restype = i32
         L.hlf_enumerate_reduce.argtypes = [fp, u64, u64, u32, vp, vp, vp, vp]
         L.hlf_sample.restype = i32
@@ -269,6 +271,21 @@ def enumerate_solutions(F: Factors, begin: int, count: int, word_bits: int,
         _check(lib().hlf_enumerate_ex(F.c, begin, count, word_bits, HLF_ORDER_COUNTER,
                                       _ptr(out) if count else None, _stream(stream)),
                "hlf_enumerate_ex")
+    return out
+
+
+def solve_dense(A: torch.Tensor, F: Factors, begin: int, count: int, word_bits: int,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """A0-A4 + E1 of one instance with n <= 64 in one launch (hlf_solve_dense):
+    the record F is written as by factor(), out[i - begin] = z_i."""
+    if A.dtype != torch.uint8 or A.dim() != 2 or A.shape[0] != A.shape[1] or A.shape[0] != F.n:
+        raise HlfError(HLF_EINVAL, "A must be a square uint8 tensor of the record's n")
+    A = A.contiguous()
+    if out is None and count:
+        out = torch.empty(count, dtype=_DTYPES[word_bits], device=F.device)
+    _check(lib().hlf_solve_dense(_ptr(A), F.c, begin, count, word_bits,
+                                 _ptr(out) if count else None, _stream(stream)),
+           "hlf_solve_dense")
     return out
 
 

@@ -131,3 +131,21 @@ def test_host_detected_errors_of_order_and_verification_calls():
     assert L.hlf_membership(ctypes.byref(with_kernel), None, 3, p, None) == hlf.HLF_EINVAL
     assert L.hlf_membership(ctypes.byref(with_kernel), p, 3, None, None) == hlf.HLF_EINVAL
     assert L.hlf_membership(ctypes.byref(with_kernel), None, 0, None, None) == hlf.HLF_OK
+
+
+def test_host_detected_errors_of_solve_dense():
+    L = hlf.lib()
+    p = ctypes.c_void_p(16)
+    f20, f100 = _rec(20), _rec(100)
+    # NULL A, n > 64, word size below n or not 16/32/64
+    assert L.hlf_solve_dense(None, ctypes.byref(f20), 0, 8, 32, p, None) == hlf.HLF_EINVAL
+    assert L.hlf_solve_dense(p, ctypes.byref(f100), 0, 8, 64, p, None) == hlf.HLF_EINVAL
+    assert L.hlf_solve_dense(p, ctypes.byref(f20), 0, 8, 16, p, None) == hlf.HLF_EINVAL
+    assert L.hlf_solve_dense(p, ctypes.byref(f20), 0, 8, 24, p, None) == hlf.HLF_EINVAL
+    # misaligned begin (a multiple of 4 for uint32) or output, NULL output
+    assert L.hlf_solve_dense(p, ctypes.byref(f20), 2, 8, 32, p, None) == hlf.HLF_EINVAL
+    assert L.hlf_solve_dense(p, ctypes.byref(f20), 0, 8, 32, ctypes.c_void_p(24), None) == hlf.HLF_EINVAL
+    assert L.hlf_solve_dense(p, ctypes.byref(f20), 0, 8, 32, None, None) == hlf.HLF_EINVAL
+    # a NULL record member
+    bad = _rec(20, "basis")
+    assert L.hlf_solve_dense(p, ctypes.byref(bad), 0, 8, 32, p, None) == hlf.HLF_EINVAL
