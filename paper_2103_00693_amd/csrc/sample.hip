@@ -67,33 +67,32 @@ __global__ __launch_bounds__(SampleShape<WMAX>::kThreads) void sample_kernel(
 
 // ---------------------------------------------------------------------------
 // Large n: sampling as a dense product over GF(2) on the matrix cores.
-// Z = C * Bm mod 2, C the num x r coefficient bits, Bm the r x n basis bits:
-// with 0/1 int8 operands the int32 sums of v_mfma_i32_32x32x32_i8 carry the
-// GF(2) product in bit 0 (r <= 1024 < 2^31).  A workgroup owns one group of
-// 128 output bits (4 column chunks of 32); its B operands, in the register
-// layout of the instruction, are built once in LDS (ceil(r/32) x 4 chunks of
-// 64 lanes x 16 bytes).  Each wave multiplies 32 samples by them, the A
-// operand coming straight from the coefficient words.  Within a 32-wide K
-// chunk, byte t of operand dword d of lane l stands for k = 8t + d + 4h,
-// h = l / 32 (B uses the same assignment; the sum over k does not depend on
-// it): if y holds the chunk's 32 bits, dword d is (y >> (d + 4h)) &
-// 0x01010101, a shift and a mask for A and B alike, and lane l covers sample
-// row l % 32.  The product is taken as Z^T = Bm^T * C^T (the basis operand
-// first), so accumulator register i of lane l holds output bit 8*(i/4) +
-// 4*(l/32) + i%4 of the column chunk for sample l % 32: a lane assembles 16
-// bits of its sample's word and takes the other 16 from lane l ^ 32.
+// Z = C * Bm mod 2, C the num x r coefficient bits, Bm the r x n basis bits,
+// on v_mfma_i32_32x32x32_i8 (int32 sums of int8 products, exact for r <=
+// 1024).  A workgroup owns one group of 128 output bits (4 column chunks of
+// 32); its B operands, in the register layout of the instruction, are built
+// once in LDS (ceil(r/32) x 4 chunks of 64 lanes x 16 bytes).  Each wave
+// multiplies blocks of 32 samples by them, the A operand coming straight from
+// the coefficient words.
+//
+// Within a 32-wide K chunk with bits y, byte t of operand dword d of lane l
+// stands for k = 8t + d + 4h, h = l / 32, for A and B alike.  The A dword is
+// y & (0x01010101 << (d + 4h)): one AND, each byte 0 or 2^(d+4h).  The B
+// bytes, built once, are 0 or 2^(7-d-4h).  A product of two set bits is then
+// 2^7, which as int8 operands reads +128 or -128 (one factor 0x80), and both
+// are 128 mod 256: bit 7 of the int32 sum is the GF(2) product.  Lane l
+// covers sample row l % 32.  The product is taken as Z^T = Bm^T * C^T (the
+// basis operand first), so accumulator register i of lane l holds output bit
+// 8*(i/4) + 4*(l/32) + i%4 of the column chunk for sample l % 32: a lane
+// assembles 16 bits of its sample's word and takes the other 16 from lane
+// l ^ 32.
 // ---------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kMfmaJC = 4;       // 32-bit column chunks per workgroup
-constexpr int kMfmaWaves = 8;    // 32 samples per wave per pass
+constexpr int kMfmaWaves = 16;   // four per SIMD, 32 samples each at a time
 constexpr int kMfmaMaxKC = HLF_MAX_N / 32;
-
-// Operand dword d of lane half h for the chunk bits y: byte t = bit 8t+d+4h.
-__device__ __forceinline__ uint32_t chunk_bytes(uint32_t y, int d, int h) {
-    return (y >> (d + 4 * h)) & 0x01010101u;
-}
 
 __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
     FactorIn f, uint64_t seed, uint64_t num, const uint64_t *__restrict__ coeffs,
@@ -105,6 +104,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
     const int W = f.words;
     const int cg = blockIdx.x;        // words 2cg, 2cg+1 of every sample
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, m = lane & 31;
     const int KC = (r + 31) >> 5;
     const int KB = (r + 63) >> 6;
     const int w0 = 2 * cg;
@@ -119,80 +119,74 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
         BT[(64 * q + lane) * 16 + kb] = wave_transpose64(x);
     }
     __syncthreads();
-    // B operand of chunk (kc, jc): lane (h, n), dword d, byte t holds bit
-    // j = 32jc + n of B_k, k = 32kc + 8t + d + 4h.
+    // B operand of chunk (kc, jc): lane (h, n), dword d, byte t is 2^(7-d-4h)
+    // times bit j = 32jc + n of B_k, k = 32kc + 8t + d + 4h.
     for (int t = wave; t < KC * kMfmaJC; t += kMfmaWaves) {
         const int kc = t / kMfmaJC, jc = t - kc * kMfmaJC;
-        const int h = lane >> 5, nn = lane & 31;
-        const int j = 32 * jc + nn;
+        const int j = 32 * jc + m;
         const uint32_t y = (uint32_t)(BT[j * 16 + (kc >> 1)] >> (32 * (kc & 1)));
         uint32_t *dst = &Bop[((size_t)t * 64 + lane) * 4];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) dst[d] = chunk_bytes(y, d, h);
+        for (int d = 0; d < 4; ++d) dst[d] = ((y >> (d + 4 * h)) & 0x01010101u) << (7 - d - 4 * h);
     }
     __syncthreads();
 
     const uint64_t l0 = f.shift[w0], l1 = has1 ? f.shift[w0 + 1] : 0ull;
     const int R64 = (r + 63) >> 6;
     const uint64_t lastmask = (r & 63) ? ((1ull << (r & 63)) - 1ull) : ~0ull;
-    const int h = lane >> 5, m = lane & 31;
-    const uint64_t pass = 32ull * kMfmaWaves;
-    for (uint64_t s0 = (uint64_t)blockIdx.y * pass; s0 < num; s0 += (uint64_t)gridDim.y * pass) {
-        const uint64_t s = s0 + 32ull * wave + (uint64_t)m;  // this lane's A row
+    uint32_t amask[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) amask[d] = 0x01010101u << (d + 4 * h);
+    // This workgroup's samples: a contiguous run of 32-sample blocks, taken by
+    // its waves in turn (every SIMD of the CU gets the same number of blocks).
+    const uint64_t nblk = (num + 31) >> 5;
+    const uint64_t per_wg = (nblk + gridDim.y - 1) / gridDim.y;
+    const uint64_t blk_end = min(nblk, (uint64_t)(blockIdx.y + 1) * per_wg);
+    for (uint64_t blk = (uint64_t)blockIdx.y * per_wg + wave; blk < blk_end; blk += kMfmaWaves) {
+        const uint64_t s = 32ull * blk + (uint64_t)m;  // this lane's A row
         const bool live = s < num;
         v16i acc[kMfmaJC];
 #pragma unroll
         for (int jc = 0; jc < kMfmaJC; ++jc) acc[jc] = v16i{};
         // Coefficient words 2p, 2p+1 of this row cover K chunks 4p .. 4p+3:
-        // lane half h generates word 2p+h, the halves swap copies.
-        auto words_for = [&](int p, uint64_t (&cw)[2]) {
+        // lane half h generates word 2p+h (SplitMix64 state seed + (ctr+1)
+        // gamma, advanced by 2 gamma per step), the halves swap copies.
+        const uint64_t ctr0 = s * (uint64_t)R64 + (uint64_t)h;
+        uint64_t state = seed + (ctr0 + 1) * kGamma;
+        auto words_for = [&](int p, uint32_t (&y)[4]) {
             const int q = 2 * p + h;
-            const uint64_t ctr = s * (uint64_t)R64 + (uint64_t)q;
-            uint64_t mine =
-                (live && q < R64) ? (coeffs ? coeffs[ctr] : mix13(seed + (ctr + 1) * kGamma)) : 0ull;
+            uint64_t mine = 0ull;
+            if (live && q < R64) mine = coeffs ? coeffs[ctr0 + 2 * p] : mix13(state);
             if (q == R64 - 1) mine &= lastmask;
+            state += 2 * kGamma;
             const uint64_t other = __shfl_xor(mine, 32);
-            cw[0] = h ? other : mine;
-            cw[1] = h ? mine : other;
-        };
-        // A operand of K chunk kc: this lane half's 16 coefficient bits as bytes.
-        auto a_for = [&](int kc, const uint64_t (&cw)[2]) {
-            const uint32_t y = (uint32_t)(cw[(kc >> 1) & 1] >> (32 * (kc & 1)));
-            v4i a;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) a[d] = (int)chunk_bytes(y, d, h);
-            return a;
+            const uint64_t c0 = h ? other : mine, c1 = h ? mine : other;
+            y[0] = (uint32_t)c0; y[1] = (uint32_t)(c0 >> 32);
+            y[2] = (uint32_t)c1; y[3] = (uint32_t)(c1 >> 32);
         };
         auto b_for = [&](int kc, v4i (&b)[kMfmaJC]) {
 #pragma unroll
             for (int jc = 0; jc < kMfmaJC; ++jc)
                 b[jc] = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * kMfmaJC + jc) * 64 + lane) * 4]);
         };
-        uint64_t cw[2];
-        words_for(0, cw);
-        v4i b0[kMfmaJC], b1[kMfmaJC];
-        v4i a0 = a_for(0, cw), a1;
-        b_for(0, b0);
-        // Two K chunks per iteration with alternating operand registers; the
-        // operands of chunk kc+1 are read while chunk kc multiplies.
-        for (int kc = 0; kc < KC; kc += 2) {
-            const bool two = kc + 1 < KC;
-            if (two) {
-                b_for(kc + 1, b1);
-                a1 = a_for(kc + 1, cw);
-            }
+        uint32_t y[4];
+        words_for(0, y);
+        // The other waves of the SIMD cover the operand reads' latency.
+        for (int p = 0; 4 * p < KC; ++p) {
+            if (p > 0) words_for(p, y);
 #pragma unroll
-            for (int jc = 0; jc < kMfmaJC; ++jc)
-                acc[jc] = __builtin_amdgcn_mfma_i32_32x32x32_i8(b0[jc], a0, acc[jc], 0, 0, 0);
-            if (!two) break;
-            if (kc + 2 < KC) {
-                if (((kc + 2) & 3) == 0) words_for((kc + 2) >> 2, cw);
-                b_for(kc + 2, b0);
-                a0 = a_for(kc + 2, cw);
-            }
+            for (int u = 0; u < 4; ++u) {
+                const int kc = 4 * p + u;
+                if (kc >= KC) break;
+                v4i a;
 #pragma unroll
-            for (int jc = 0; jc < kMfmaJC; ++jc)
-                acc[jc] = __builtin_amdgcn_mfma_i32_32x32x32_i8(b1[jc], a1, acc[jc], 0, 0, 0);
+                for (int d = 0; d < 4; ++d) a[d] = (int)(y[u] & amask[d]);
+                v4i b[kMfmaJC];
+                b_for(kc, b);
+#pragma unroll
+                for (int jc = 0; jc < kMfmaJC; ++jc)
+                    acc[jc] = __builtin_amdgcn_mfma_i32_32x32x32_i8(b[jc], a, acc[jc], 0, 0, 0);
+            }
         }
         uint32_t word[kMfmaJC];
 #pragma unroll
@@ -200,11 +194,11 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
             uint32_t mine = 0;
 #pragma unroll
             for (int i = 0; i < 16; ++i)
-                mine |= ((uint32_t)acc[jc][i] & 1u) << (8 * (i >> 2) + (i & 3));
+                mine |= (((uint32_t)acc[jc][i] >> 7) & 1u) << (8 * (i >> 2) + (i & 3));
             mine <<= 4 * h;
             word[jc] = mine | (uint32_t)__shfl_xor((int)mine, 32);
         }
-        const uint64_t so = s0 + 32ull * wave + (uint64_t)lane;  // row `lane` for lanes < 32
+        const uint64_t so = 32ull * blk + (uint64_t)lane;  // row `lane` for lanes < 32
         if (lane < 32 && so < num) {
             out[so * W + w0] = (((uint64_t)word[1] << 32) | word[0]) ^ l0;
             if (has1) out[so * W + w0 + 1] = (((uint64_t)word[3] << 32) | word[2]) ^ l1;
@@ -216,14 +210,16 @@ hlf_status launch_sample_mfma(const FactorIn &f, uint64_t seed, uint64_t num,
                               const uint64_t *coeffs, uint64_t *out, hipStream_t stream) {
     const int W = f.words;
     const unsigned groups = (unsigned)((W + 1) / 2);
-    const uint64_t passes = (num + 32 * kMfmaWaves - 1) / (32 * kMfmaWaves);
+    const uint64_t blocks32 = (num + 31) / 32;
     // One workgroup per CU fits (the B operands take 128 KiB of LDS); every
-    // workgroup builds them once and loops over passes of 256 samples.
+    // workgroup builds them once and takes a contiguous run of 32-sample
+    // blocks, at least one per wave.
     uint64_t y = (uint64_t)device_cu_count() / groups;
-    if (y > passes) y = passes;
+    const uint64_t most = (blocks32 + kMfmaWaves - 1) / kMfmaWaves;
+    if (y > most) y = most;
     if (y == 0) y = 1;
-    hipLaunchKernelGGL(sample_mfma_kernel, dim3(groups, (unsigned)y), dim3(64 * kMfmaWaves), 0,
-                       stream, f, seed, num, coeffs, out);
+    hipLaunchKernelGGL(sample_mfma_kernel, dim3(groups, (unsigned)y),
+                       dim3(64 * kMfmaWaves), 0, stream, f, seed, num, coeffs, out);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
 }
 
