@@ -42,7 +42,7 @@ REDUCE_VALU_OPS_PER_SOLUTION = 17
 # 10,200,547,328 solutions = 19.02 lane operations per solution (the full-tile
 # loop plus per-tile and per-wave work).  The roofline uses it while the
 # kernel's sources are the measured ones, else the loop count above.
-REDUCE_VALU_MEASURED = {"src_sha256_16": "af6ef5bcfdc21084", "ops_per_solution": 19.02}
+REDUCE_VALU_MEASURED = {"src_sha256_16": "cbd8450aca25468c", "ops_per_solution": 19.02}
 REDUCE_VALU_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/enumerate.hip",
                        "paper_2103_00693_amd/csrc/hlf_device.h")
 # HBM traffic of one batch_enum_kernel<uint32_t, overlap> launch of the headline step,
@@ -50,8 +50,8 @@ REDUCE_VALU_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_a
 # dispatch), each scaled by what the same counter reads for a plain 256 MiB
 # device copy (WRITE_SIZE 262144 KiB -> x1.0, FETCH_SIZE 131085 KiB -> x2.0).
 # Valid only for the kernel sources it was taken on (sha256 prefix below).
-ENUM_TRAFFIC = {"src_sha256_16": "05f6f3615be0f93e", "fetch_kib_raw": 80.6, "fetch_scale": 2.0,
-                "write_kib_raw": 688687.0, "write_scale": 1.0}
+ENUM_TRAFFIC = {"src_sha256_16": "478b4173630bcbf7", "fetch_kib_raw": 67.1, "fetch_scale": 2.0,
+                "write_kib_raw": 688762.0, "write_scale": 1.0}
 ENUM_TRAFFIC_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/batch.hip",
                         "paper_2103_00693_amd/csrc/factor_wave.h",
                         "paper_2103_00693_amd/csrc/hlf_device.h")

@@ -139,6 +139,7 @@ __global__ __launch_bounds__(kTileThreads, 8) void batch_enum_kernel(EnumTasks t
         }
         bid -= job.blocks;
     }
+    bid = xcd_block(bid, gridDim.x - (kFactor ? job.blocks : 0u));
     int k = 0;
     for (int j = 1; j < tasks.num; ++j)
         if (tasks.t[j].block0 <= bid) k = j;

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kTileThreads) void enum_tile_kernel(FactorIn f, uin
     }
     const uint64_t end = begin + count;
     const uint64_t ntiles = ((end - 1) >> S) - (begin >> S) + 1;
-    const uint64_t t0 = (uint64_t)blockIdx.x * tiles_per_block;
+    const uint64_t t0 = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * tiles_per_block;
     if (t0 >= ntiles) return;
     const uint64_t t1 = (t0 + tiles_per_block < ntiles) ? t0 + tiles_per_block : ntiles;
     enum_tiles_w1<T>(Bx, f.shift[0], begin, count, out, t0, t1);
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kTileThreads) void enum_wide_tile_kernel(FactorIn f
     }
     const uint64_t end = begin + count;
     const uint64_t ntiles = ((end - 1) >> S) - (begin >> S) + 1;
-    const uint64_t t0 = (uint64_t)blockIdx.x * tiles_per_block;
+    const uint64_t t0 = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * tiles_per_block;
     if (t0 >= ntiles) return;
     const uint64_t t1 = (t0 + tiles_per_block < ntiles) ? t0 + tiles_per_block : ntiles;
 
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kTileThreads) void circuit_tile_kernel(
     }
     const uint64_t end = begin + count;
     const uint64_t ntiles = ((end - 1) >> S) - (begin >> S) + 1;
-    const uint64_t t0 = (uint64_t)blockIdx.x * tiles_per_block;
+    const uint64_t t0 = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * tiles_per_block;
     if (t0 >= ntiles) return;
     const uint64_t t1 = (t0 + tiles_per_block < ntiles) ? t0 + tiles_per_block : ntiles;
     uint64_t Tt = (begin >> S) + t0;

@@ -121,6 +121,17 @@ constexpr uint64_t kTileBytes = 16ull * kTileThreads;
 // Grids up to this many workgroups seed their lane constants the short way.
 constexpr unsigned kShortSeedGrid = 512;
 
+// Workgroups are dealt to the 8 XCDs in turn, so dispatch index b runs on XCD
+// b % 8.  xcd_block maps b (of n) to the block index it materialises such that
+// each XCD's workgroups take one contiguous run of blocks, in order: XCD x
+// takes the q or q + 1 blocks from x*q + min(x, n % 8) on, q = n / 8.  Stores
+// from one XCD then stay in one region instead of interleaving with the other
+// seven XCDs' every 128 KiB, which the HBM write rate favours.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
+    const uint32_t x = b & 7u, q = n >> 3, rem = n & 7u;
+    return x * q + (x < rem ? x : rem) + (b >> 3);
+}
+
 template <typename T>
 __host__ __device__ constexpr int tile_shift() {
     return kLogTileThreads + Vec<T>::LOGV;
