@@ -91,6 +91,38 @@ def test_ragged_and_unaligned_ranges(word_bits):
         assert np.array_equal(got, ref_enum(Fo, begin, count)[:, 0]), (begin, count)
 
 
+
+@pytest.mark.parametrize("blocks", [515, 517, 1021])
+def test_xcd_dealing_ragged_block_counts(blocks):
+    # Launches of more than 512 workgroups whose count is not a multiple of
+    # the 8 XCDs: each XCD takes one contiguous run of 128 KiB ranges, the
+    # later workgroups seed their lane constants the per-index way, and the
+    # last range is short.  The whole output is compared.
+    A = grid_instance(5, seed=2)  # r = 25
+    Fo = O.factor(A)
+    F, _ = gpu_factor(A)
+    per_block = 8 * 4096  # 8 tiles of 4096 uint32 solutions
+    begin = 4
+    count = per_block * (blocks - 1) + 4096 * 5 + 7  # 8*blocks - 2 tiles
+    assert begin + count <= 1 << Fo["rank"]
+    print(f"[enum] xcd dealing blocks={blocks} count={count}", flush=True)
+    got = narrow_to_u64(gpu_enum(F, begin, count, 32))
+    assert np.array_equal(got, ref_enum(Fo, begin, count)[:, 0])
+
+
+def test_xcd_dealing_multiword_large_ragged():
+    # The W = 2 kernel over more than 512 workgroups with a ragged tail.
+    A = _embedded(100, 26, 5)  # r = 24
+    Fo = O.factor(A)
+    r = Fo["rank"]
+    assert r >= 24
+    F, _ = gpu_factor(A)
+    # tiles of 1024 indices, 16 per workgroup: 8261 tiles, 517 workgroups
+    begin, count = 3, 1024 * 8260 + 11
+    print(f"[enum] xcd dealing multiword r={r} count={count}", flush=True)
+    got = gpu_enum(F, begin, count, 128)
+    assert np.array_equal(hlf.as_uint64(got).reshape(count, 2), ref_enum(Fo, begin, count))
+
 def test_misaligned_output_pointer():
     A = grid_instance(5, seed=4)
     Fo = O.factor(A)
