@@ -55,6 +55,8 @@ ENUM_TRAFFIC = {"src_sha256_16": "478b4173630bcbf7", "fetch_kib_raw": 67.1, "fet
 ENUM_TRAFFIC_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/batch.hip",
                         "paper_2103_00693_amd/csrc/factor_wave.h",
                         "paper_2103_00693_amd/csrc/hlf_device.h")
+# Streams that take the headline steps in turn (launches in flight).
+HEADLINE_STREAMS = 2
 METRIC = "solutions enumerated/s (G/s) + % HBM/VALU roofline; batched instances/s, p99 latency"
 
 
@@ -431,25 +433,26 @@ def main():
 
     # ---------------- headline workload: N=5 grid, 8 seeds ----------------
     # Step k is ONE launch (hlf_batch_enumerate_overlap): it materialises all
-    # 2^r solutions of the 8 instances from record set k % 4 and, in extra
+    # 2^r solutions of the 8 instances from record set k % 2S and, in extra
     # workgroups of the same launch, runs stage 1 (pack + validate + factor)
-    # of the 8 instances into record set (k+2) % 4 for step k+2.  Steps
-    # alternate between two streams with an output set each, so two launches
-    # are in flight and each one's start-up and drain overlap the other's; a
-    # launch depends only on the launch two steps back, on its own stream.
-    # Stage 1 of the first two timed steps ran in the last warm-up launches;
-    # the last two timed launches run stage 1 for steps past the timed ones,
-    # so the timed region holds exactly `steps` stage-1 and `steps` stage-2
-    # passes.
+    # of the 8 instances into record set (k+S) % 2S for step k+S, S =
+    # HEADLINE_STREAMS.  Steps go to the S streams in turn, each with its own
+    # output set, so S launches are in flight and each one's start-up and
+    # drain overlap the others'; a launch depends only on the launch S steps
+    # back, on its own stream.  Stage 1 of the first S timed steps ran in the
+    # last warm-up launches; the last S timed launches run stage 1 for steps
+    # past the timed ones, so the timed region holds exactly `steps` stage-1
+    # and `steps` stage-2 passes.
     n = 25
     mats = [grid_instance(5, seed=s) for s in CONFIG2_SEEDS]
-    Bs = [hlf.Batch([n] * len(mats)) for _ in range(4)]
+    n_streams = HEADLINE_STREAMS
+    Bs = [hlf.Batch([n] * len(mats)) for _ in range(2 * n_streams)]
     A = Bs[0].dense_input(mats, device=dev)
-    streams = [stream, torch.cuda.Stream()]
-    Bs[0].factor_dense(A, stream=stream)
-    Bs[1].factor_dense(A, stream=stream)
+    streams = [stream] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
+    for Bk in Bs[:n_streams]:
+        Bk.factor_dense(A, stream=stream)
     stream.synchronize()
-    if not all(st == hlf.HLF_OK for Bk in Bs[:2] for st in Bk.statuses()):
+    if not all(st == hlf.HLF_OK for Bk in Bs[:n_streams] for st in Bk.statuses()):
         raise RuntimeError("factor failed")
     ranks = [int(r) for r in Bs[0].ranks()]
     counts = [1 << r for r in ranks]
@@ -461,36 +464,40 @@ def main():
     bytes_per_step = 4 * solutions_per_step
 
     def step(k):
-        Bs[k % 4].enumerate_overlap(inst, zeros, counts, out_sets[k % 2], 32, Bs[(k + 2) % 4], A,
-                                    stream=streams[k % 2])
+        Bs[k % (2 * n_streams)].enumerate_overlap(inst, zeros, counts, out_sets[k % n_streams], 32,
+                                                  Bs[(k + n_streams) % (2 * n_streams)], A,
+                                                  stream=streams[k % n_streams])
 
-    warmup = max(2, args.warmup)
+    warmup = max(n_streams, args.warmup)
     for k in range(warmup):
         step(k)
     torch.cuda.synchronize()
 
-    # HIP events: ev0 on stream 0 before the first timed launch (stream 1
-    # waits for it), ev1 on stream 0 after stream 1's last launch has been
-    # joined, so ev0..ev1 covers every timed launch of both streams.
+    # HIP events: ev0 on stream 0 before the first timed launch (the other
+    # streams wait for it), ev1 on stream 0 after the other streams' last
+    # launches have been joined, so ev0..ev1 covers every timed launch.
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    join = torch.cuda.Event()
+    joins = [torch.cuda.Event() for _ in streams[1:]]
     t0 = time.perf_counter()
     ev0.record(streams[0])
-    streams[1].wait_event(ev0)
+    for st in streams[1:]:
+        st.wait_event(ev0)
     for k in range(args.steps):
         step(warmup + k)
-    join.record(streams[1])
-    streams[0].wait_event(join)
+    for st, j in zip(streams[1:], joins):
+        j.record(st)
+        streams[0].wait_event(j)
     ev1.record(streams[0])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for Bk in Bs:
         if not all(st == hlf.HLF_OK for st in Bk.statuses()):
             raise RuntimeError("enumerate failed")
-    for a, b in zip(out_sets[0], out_sets[1]):
-        if not torch.equal(a, b):
-            raise RuntimeError("the two streams' outputs differ")
+    for other in out_sets[1:]:
+        for a, b in zip(out_sets[0], other):
+            if not torch.equal(a, b):
+                raise RuntimeError("the streams' outputs differ")
 
     # the same step as ONE launch (hlf_batch_solve), for comparison
     Bs[0].solve(A, inst, zeros, counts, outs, 32, stream=stream)
@@ -507,7 +514,7 @@ def main():
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = solutions_per_step * args.steps / elapsed / 1e9
-    # average time per launch with two in flight: the events' span / launches
+    # average time per launch with n_streams in flight: the events' span / launches
     launch_ms = ev0.elapsed_time(ev1) / args.steps
     achieved_gbs = bytes_per_step / (launch_ms * 1e-3) / 1e9
 
@@ -540,7 +547,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
             "traffic": enum_traffic_bytes(),
-            "launches_in_flight": 2,
+            "launches_in_flight": n_streams,
             "launch_interval_us": round(1e3 * launch_ms, 3),
             "algorithmic_bytes_per_launch": bytes_per_step,
             "fused_one_launch_step_us": round(fused_us, 2),

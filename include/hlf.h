@@ -336,11 +336,11 @@ hlf_status hlf_batch_enumerate(hlf_batch b, int32_t num, const int32_t *inst,
  * `next` while the others materialise b.  Nothing in the launch reads the
  * records it writes, so a pipeline alternates two batches: launch k
  * materialises the instances factored by launch k-1 and factors those of
- * launch k+1.  With two streams taking alternate steps, launch k factors for
- * launch k+2 on the same stream, four batches in rotation and a separate
- * output set per stream: no launch then touches the records or outputs of the
- * launch running beside it, and each one's start-up and drain overlap the
- * other's.  next must differ from b (HLF_EINVAL otherwise).                  */
+ * launch k+1.  With S streams taking the steps in turn, launch k factors for
+ * launch k+S on the same stream, 2S batches in rotation and a separate output
+ * set per stream: no launch then touches the records or outputs of the
+ * launches running beside it, and each one's start-up and drain overlap the
+ * others'.  next must differ from b (HLF_EINVAL otherwise).                  */
 hlf_status hlf_batch_enumerate_overlap(hlf_batch b, int32_t num, const int32_t *inst,
                                        const uint64_t *begin, const uint64_t *count,
                                        void *const *out, int32_t word_bits, hlf_batch next,

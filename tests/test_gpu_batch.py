@@ -340,30 +340,31 @@ def test_batch_enumerate_overlap_pipeline():
         Bs[0].enumerate_overlap([0], [0], [16], [outs[0]], 32, Bs[0], A)
 
 
-def test_batch_enumerate_overlap_two_streams():
-    # Two streams take alternate steps; launch k materialises record set k % 4
-    # and factors record set (k + 2) % 4 for the next launch on its own stream,
-    # writing output set k % 2.  Two launches run at once and every one of
-    # them must still produce the full solution sets and records.
+@pytest.mark.parametrize("S", [2, 3])
+def test_batch_enumerate_overlap_several_streams(S):
+    # S streams take the steps in turn; launch k materialises record set
+    # k % 2S and factors record set (k + S) % 2S for the next launch on its
+    # own stream, writing output set k % S.  S launches run at once and every
+    # one of them must still produce the full solution sets and records.
     mats = [grid_instance(5, seed=s) for s in CONFIG2_SEEDS[:3]] + [grid_instance(4, seed=2)]
     Fs = [O.factor(m) for m in mats]
     ns = [m.shape[0] for m in mats]
-    Bs = [hlf.Batch(ns) for _ in range(4)]
+    Bs = [hlf.Batch(ns) for _ in range(2 * S)]
     A = Bs[0].dense_input(mats)
-    Bs[0].factor_dense(A)
-    Bs[1].factor_dense(A)
+    for Bk in Bs[:S]:
+        Bk.factor_dense(A)
     torch.cuda.synchronize()
     counts = [1 << F["rank"] for F in Fs]
     refs = [C.enumerate_range(F, 0, c)[:, 0] for F, c in zip(Fs, counts)]
     out_sets = [[torch.full((c,), -1, dtype=torch.int32, device="cuda") for c in counts]
-                for _ in range(2)]
-    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
-    steps = 10
-    print(f"[batch] two-stream overlap, {steps} steps", flush=True)
+                for _ in range(S)]
+    streams = [torch.cuda.Stream() for _ in range(S)]
+    steps = 5 * S
+    print(f"[batch] {S}-stream overlap, {steps} steps", flush=True)
     for k in range(steps):
-        Bs[k % 4].enumerate_overlap(list(range(len(mats))), [0] * len(mats), counts,
-                                    out_sets[k % 2], 32, Bs[(k + 2) % 4], A,
-                                    stream=streams[k % 2])
+        Bs[k % (2 * S)].enumerate_overlap(list(range(len(mats))), [0] * len(mats), counts,
+                                          out_sets[k % S], 32, Bs[(k + S) % (2 * S)], A,
+                                          stream=streams[k % S])
     torch.cuda.synchronize()
     for outs in out_sets:
         for s, o in enumerate(outs):
@@ -371,4 +372,4 @@ def test_batch_enumerate_overlap_two_streams():
     for j, Bk in enumerate(Bs):
         recs = Bk.records()
         for s, F in enumerate(Fs):
-            check_record(recs[s], F, f"two-stream record set {j} instance {s}")
+            check_record(recs[s], F, f"{S}-stream record set {j} instance {s}")
