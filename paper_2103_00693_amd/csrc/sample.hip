@@ -68,36 +68,41 @@ __global__ __launch_bounds__(SampleShape<WMAX>::kThreads) void sample_kernel(
 // ---------------------------------------------------------------------------
 // Large n: sampling as a dense product over GF(2) on the matrix cores.
 // Z = C * Bm mod 2, C the num x r coefficient bits, Bm the r x n basis bits,
-// on v_mfma_i32_32x32x32_i8 (int32 sums of int8 products, exact for r <=
-// 1024).  A workgroup owns one group of 128 output bits (4 column chunks of
+// on v_mfma_scale_f32_32x32x64_f8f6f4 with 4-bit E2M1 operands (scale 1):
+// fp32 sums of products that are 0 or exactly 1, so a sum is the integer
+// count of common set bits (<= r <= 1024, exact) and its bit 0 is the GF(2)
+// product.  A workgroup owns one group of 128 output bits (4 column chunks of
 // 32); its B operands, in the register layout of the instruction, are built
-// once in LDS (ceil(r/32) x 4 chunks of 64 lanes x 16 bytes).  Each wave
+// once in LDS (ceil(r/64) x 4 chunks of 64 lanes x 16 bytes).  Each wave
 // multiplies blocks of 32 samples by them, the A operand coming straight from
 // the coefficient words.
 //
-// Within a 32-wide K chunk with bits y, byte t of operand dword d of lane l
-// stands for k = 8t + d + 4h, h = l / 32, for A and B alike.  The A dword is
-// y & (0x01010101 << (d + 4h)): one AND, each byte 0 or 2^(d+4h).  The B
-// bytes, built once, are 0 or 2^(7-d-4h).  A product of two set bits is then
-// 2^7, which as int8 operands reads +128 or -128 (one factor 0x80), and both
-// are 128 mod 256: bit 7 of the int32 sum is the GF(2) product.  Lane l
-// covers sample row l % 32.  The product is taken as Z^T = Bm^T * C^T (the
-// basis operand first), so accumulator register i of lane l holds output bit
-// 8*(i/4) + 4*(l/32) + i%4 of the column chunk for sample l % 32: a lane
-// assembles 16 bits of its sample's word and takes the other 16 from lane
-// l ^ 32.
+// K chunk kc is coefficient word kc: lane l covers sample row l % 32 and the
+// 32-bit half h = l / 32 of the word, y.  Nibble t of operand dword d stands
+// for k = 64kc + 32h + 4t + d, for A and B alike.  A single set bit of an
+// E2M1 nibble reads 0.5, 1 or 2 at positions 0, 1, 2 (position 3 is the
+// sign), so the A dwords are y & 0x11111111, y & 0x22222222, y & 0x44444444
+// and (y >> 1) & 0x44444444 (positions 0, 1, 2, 2), and the B nibbles, built
+// once, put their bits at positions 2, 1, 0, 0: every product of two set
+// bits is 1.  The product is taken as Z^T = Bm^T * C^T (the basis operand
+// first), so accumulator register i of lane l holds output bit 8*(i/4) +
+// 4*(l/32) + i%4 of the column chunk for sample l % 32: a lane assembles 16
+// bits of its sample's word and takes the other 16 from lane l ^ 32.
 // ---------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kMfmaJC = 4;       // 32-bit column chunks per workgroup
 constexpr int kMfmaWaves = 16;   // four per SIMD, 32 samples each at a time
-constexpr int kMfmaMaxKC = HLF_MAX_N / 32;
+constexpr int kMfmaMaxKC = HLF_MAX_N / 64;
+constexpr int kE2M1 = 4;         // operand format code of the instruction
+constexpr int kScaleOne = 127;   // E8M0 scale 2^0
 
 __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
     FactorIn f, uint64_t seed, uint64_t num, const uint64_t *__restrict__ coeffs,
     uint64_t *__restrict__ out) {
-    __shared__ __align__(16) uint32_t Bop[kMfmaMaxKC * kMfmaJC * 64 * 4];  // 128 KiB
+    __shared__ __align__(16) uint32_t Bop[kMfmaMaxKC * kMfmaJC * 64 * 4];  // 64 KiB
     __shared__ uint64_t BT[128 * 16];                                    // 16 KiB
     if (*(volatile int32_t *)f.status != HLF_OK) return;
     const int r = *f.rank;
@@ -105,38 +110,36 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
     const int cg = blockIdx.x;        // words 2cg, 2cg+1 of every sample
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, m = lane & 31;
-    const int KC = (r + 31) >> 5;
-    const int KB = (r + 63) >> 6;
+    const int KC = (r + 63) >> 6;     // K chunks of 64 = coefficient words
     const int w0 = 2 * cg;
     const bool has1 = w0 + 1 < W;
-    // Transpose: BT[j * 16 + kb] bit t = bit j (of this group's 128 columns)
-    // of B_{64kb+t}.  A wave takes one (kb, word) tile: lane t holds the word
-    // of row 64kb+t, and after the transpose lane b holds column b.
-    for (int t = wave; t < 2 * KB; t += kMfmaWaves) {
-        const int kb = t >> 1, q = t & 1;
-        const int k = 64 * kb + lane;
+    // Transpose: BT[j * 16 + kc] bit t = bit j (of this group's 128 columns)
+    // of B_{64kc+t}.  A wave takes one (kc, word) tile: lane t holds the word
+    // of row 64kc+t, and after the transpose lane b holds column b.
+    for (int t = wave; t < 2 * KC; t += kMfmaWaves) {
+        const int kc = t >> 1, q = t & 1;
+        const int k = 64 * kc + lane;
         const uint64_t x = (k < r && (q == 0 || has1)) ? f.basis[(size_t)k * W + w0 + q] : 0ull;
-        BT[(64 * q + lane) * 16 + kb] = wave_transpose64(x);
+        BT[(64 * q + lane) * 16 + kc] = wave_transpose64(x);
     }
     __syncthreads();
-    // B operand of chunk (kc, jc): lane (h, n), dword d, byte t is 2^(7-d-4h)
-    // times bit j = 32jc + n of B_k, k = 32kc + 8t + d + 4h.
+    // B operand of chunk (kc, jc): lane (h, n), dword d, nibble t holds bit
+    // j = 32jc + n of B_k, k = 64kc + 32h + 4t + d, at nibble position 2, 1,
+    // 0, 0 for d = 0, 1, 2, 3.
     for (int t = wave; t < KC * kMfmaJC; t += kMfmaWaves) {
         const int kc = t / kMfmaJC, jc = t - kc * kMfmaJC;
         const int j = 32 * jc + m;
-        const uint32_t y = (uint32_t)(BT[j * 16 + (kc >> 1)] >> (32 * (kc & 1)));
+        const uint32_t y = (uint32_t)(BT[j * 16 + kc] >> (32 * h));
         uint32_t *dst = &Bop[((size_t)t * 64 + lane) * 4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) dst[d] = ((y >> (d + 4 * h)) & 0x01010101u) << (7 - d - 4 * h);
+        dst[0] = (y & 0x11111111u) << 2;
+        dst[1] = y & 0x22222222u;
+        dst[2] = (y & 0x44444444u) >> 2;
+        dst[3] = (y & 0x88888888u) >> 3;
     }
     __syncthreads();
 
     const uint64_t l0 = f.shift[w0], l1 = has1 ? f.shift[w0 + 1] : 0ull;
-    const int R64 = (r + 63) >> 6;
     const uint64_t lastmask = (r & 63) ? ((1ull << (r & 63)) - 1ull) : ~0ull;
-    uint32_t amask[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) amask[d] = 0x01010101u << (d + 4 * h);
     // This workgroup's samples: a contiguous run of 32-sample blocks, taken by
     // its waves in turn (every SIMD of the CU gets the same number of blocks).
     const uint64_t nblk = (num + 31) >> 5;
@@ -145,47 +148,40 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
     for (uint64_t blk = (uint64_t)blockIdx.y * per_wg + wave; blk < blk_end; blk += kMfmaWaves) {
         const uint64_t s = 32ull * blk + (uint64_t)m;  // this lane's A row
         const bool live = s < num;
-        v16i acc[kMfmaJC];
+        v16f acc[kMfmaJC];
 #pragma unroll
-        for (int jc = 0; jc < kMfmaJC; ++jc) acc[jc] = v16i{};
-        // Coefficient words 2p, 2p+1 of this row cover K chunks 4p .. 4p+3:
-        // lane half h generates word 2p+h (SplitMix64 state seed + (ctr+1)
-        // gamma, advanced by 2 gamma per step), the halves swap copies.
-        const uint64_t ctr0 = s * (uint64_t)R64 + (uint64_t)h;
+        for (int jc = 0; jc < kMfmaJC; ++jc) acc[jc] = v16f{};
+        // Coefficient words 2p, 2p+1 of this row are K chunks 2p, 2p+1: lane
+        // half h generates word 2p+h (SplitMix64 state seed + (ctr+1) gamma,
+        // advanced by 2 gamma per step).  One swap of the upper 32 lanes of
+        // its low dword with the lower 32 lanes of its high dword then leaves
+        // every lane the 32-bit half h of word 2p (ys[0]) and of word 2p+1
+        // (ys[1]); lanes m and m + 32 cover the same row.
+        const uint64_t ctr0 = s * (uint64_t)KC + (uint64_t)h;
         uint64_t state = seed + (ctr0 + 1) * kGamma;
-        auto words_for = [&](int p, uint32_t (&y)[4]) {
+        // The other waves of the SIMD cover the operand reads' latency.
+        for (int p = 0; 2 * p < KC; ++p) {
             const int q = 2 * p + h;
             uint64_t mine = 0ull;
-            if (live && q < R64) mine = coeffs ? coeffs[ctr0 + 2 * p] : mix13(state);
-            if (q == R64 - 1) mine &= lastmask;
+            if (live && q < KC) mine = coeffs ? coeffs[ctr0 + 2 * p] : mix13(state);
+            if (q == KC - 1) mine &= lastmask;
             state += 2 * kGamma;
-            const uint64_t other = __shfl_xor(mine, 32);
-            const uint64_t c0 = h ? other : mine, c1 = h ? mine : other;
-            y[0] = (uint32_t)c0; y[1] = (uint32_t)(c0 >> 32);
-            y[2] = (uint32_t)c1; y[3] = (uint32_t)(c1 >> 32);
-        };
-        auto b_for = [&](int kc, v4i (&b)[kMfmaJC]) {
+            const auto ys = __builtin_amdgcn_permlane32_swap((uint32_t)mine, (uint32_t)(mine >> 32),
+                                                             false, false);
 #pragma unroll
-            for (int jc = 0; jc < kMfmaJC; ++jc)
-                b[jc] = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * kMfmaJC + jc) * 64 + lane) * 4]);
-        };
-        uint32_t y[4];
-        words_for(0, y);
-        // The other waves of the SIMD cover the operand reads' latency.
-        for (int p = 0; 4 * p < KC; ++p) {
-            if (p > 0) words_for(p, y);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int kc = 4 * p + u;
+            for (int u = 0; u < 2; ++u) {
+                const int kc = 2 * p + u;
                 if (kc >= KC) break;
-                v4i a;
+                const uint32_t y = ys[u];
+                const v8i a = {(int)(y & 0x11111111u), (int)(y & 0x22222222u),
+                               (int)(y & 0x44444444u), (int)((y >> 1) & 0x44444444u), 0, 0, 0, 0};
 #pragma unroll
-                for (int d = 0; d < 4; ++d) a[d] = (int)(y[u] & amask[d]);
-                v4i b[kMfmaJC];
-                b_for(kc, b);
-#pragma unroll
-                for (int jc = 0; jc < kMfmaJC; ++jc)
-                    acc[jc] = __builtin_amdgcn_mfma_i32_32x32x32_i8(b[jc], a, acc[jc], 0, 0, 0);
+                for (int jc = 0; jc < kMfmaJC; ++jc) {
+                    const v4i b4 = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * kMfmaJC + jc) * 64 + lane) * 4]);
+                    const v8i b = {b4[0], b4[1], b4[2], b4[3], 0, 0, 0, 0};
+                    acc[jc] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        b, a, acc[jc], kE2M1, kE2M1, 0, kScaleOne, 0, kScaleOne);
+                }
             }
         }
         uint32_t word[kMfmaJC];
@@ -194,9 +190,10 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
             uint32_t mine = 0;
 #pragma unroll
             for (int i = 0; i < 16; ++i)
-                mine |= (((uint32_t)acc[jc][i] >> 7) & 1u) << (8 * (i >> 2) + (i & 3));
+                mine |= ((uint32_t)acc[jc][i] & 1u) << (8 * (i >> 2) + (i & 3));
             mine <<= 4 * h;
-            word[jc] = mine | (uint32_t)__shfl_xor((int)mine, 32);
+            // lanes 0..31 (the ones that store) take the bits of lane + 32
+            word[jc] = mine | __builtin_amdgcn_permlane32_swap(mine, mine, false, false)[1];
         }
         const uint64_t so = 32ull * blk + (uint64_t)lane;  // row `lane` for lanes < 32
         if (lane < 32 && so < num) {
@@ -211,9 +208,10 @@ hlf_status launch_sample_mfma(const FactorIn &f, uint64_t seed, uint64_t num,
     const int W = f.words;
     const unsigned groups = (unsigned)((W + 1) / 2);
     const uint64_t blocks32 = (num + 31) / 32;
-    // One workgroup per CU fits (the B operands take 128 KiB of LDS); every
-    // workgroup builds them once and takes a contiguous run of 32-sample
-    // blocks, at least one per wave.
+    // One workgroup per CU (16 waves of about 100 VGPRs; 80 KiB of LDS for
+    // the B operands and their transpose); every workgroup builds the
+    // operands once and takes a contiguous run of 32-sample blocks, at least
+    // one per wave.
     uint64_t y = (uint64_t)device_cu_count() / groups;
     const uint64_t most = (blocks32 + kMfmaWaves - 1) / kMfmaWaves;
     if (y > most) y = most;
