@@ -149,48 +149,65 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
         const uint64_t s = 32ull * blk + (uint64_t)m;  // this lane's A row
         const bool live = s < num;
         v16f acc[kMfmaJC];
-#pragma unroll
-        for (int jc = 0; jc < kMfmaJC; ++jc) acc[jc] = v16f{};
         // Coefficient words 2p, 2p+1 of this row are K chunks 2p, 2p+1: lane
         // half h generates word 2p+h (SplitMix64 state seed + (ctr+1) gamma,
         // advanced by 2 gamma per step).  One swap of the upper 32 lanes of
         // its low dword with the lower 32 lanes of its high dword then leaves
-        // every lane the 32-bit half h of word 2p (ys[0]) and of word 2p+1
-        // (ys[1]); lanes m and m + 32 cover the same row.
+        // every lane the 32-bit half h of word 2p (first) and of word 2p+1
+        // (second); lanes m and m + 32 cover the same row.
         const uint64_t ctr0 = s * (uint64_t)KC + (uint64_t)h;
         uint64_t state = seed + (ctr0 + 1) * kGamma;
-        // The other waves of the SIMD cover the operand reads' latency.
-        for (int p = 0; 2 * p < KC; ++p) {
+        auto words = [&](int p) {
             const int q = 2 * p + h;
             uint64_t mine = 0ull;
             if (live && q < KC) mine = coeffs ? coeffs[ctr0 + 2 * p] : mix13(state);
             if (q == KC - 1) mine &= lastmask;
             state += 2 * kGamma;
-            const auto ys = __builtin_amdgcn_permlane32_swap((uint32_t)mine, (uint32_t)(mine >> 32),
-                                                             false, false);
+            return __builtin_amdgcn_permlane32_swap((uint32_t)mine, (uint32_t)(mine >> 32), false, false);
+        };
+        // The products of K chunk kc; the first chunk starts from a zero
+        // accumulator (an inline constant of the instruction).
+        auto chunk = [&](int kc, uint32_t y, bool first) {
+            const v8i a = {(int)(y & 0x11111111u), (int)(y & 0x22222222u),
+                           (int)(y & 0x44444444u), (int)((y >> 1) & 0x44444444u), 0, 0, 0, 0};
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int kc = 2 * p + u;
-                if (kc >= KC) break;
-                const uint32_t y = ys[u];
-                const v8i a = {(int)(y & 0x11111111u), (int)(y & 0x22222222u),
-                               (int)(y & 0x44444444u), (int)((y >> 1) & 0x44444444u), 0, 0, 0, 0};
+            for (int jc = 0; jc < kMfmaJC; ++jc) {
+                const v4i b4 = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * kMfmaJC + jc) * 64 + lane) * 4]);
+                const v8i b = {b4[0], b4[1], b4[2], b4[3], 0, 0, 0, 0};
+                acc[jc] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    b, a, first ? v16f{} : acc[jc], kE2M1, kE2M1, 0, kScaleOne, 0, kScaleOne);
+            }
+        };
+        // The other waves of the SIMD cover the operand reads' latency.
+        if (KC == 0) {
 #pragma unroll
-                for (int jc = 0; jc < kMfmaJC; ++jc) {
-                    const v4i b4 = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * kMfmaJC + jc) * 64 + lane) * 4]);
-                    const v8i b = {b4[0], b4[1], b4[2], b4[3], 0, 0, 0, 0};
-                    acc[jc] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        b, a, acc[jc], kE2M1, kE2M1, 0, kScaleOne, 0, kScaleOne);
-                }
+            for (int jc = 0; jc < kMfmaJC; ++jc) acc[jc] = v16f{};
+        } else {
+            auto ys = words(0);
+            chunk(0, ys[0], true);
+            if (KC > 1) chunk(1, ys[1], false);
+            for (int p = 1; 2 * p < KC; ++p) {
+                ys = words(p);
+                chunk(2 * p, ys[0], false);
+                if (2 * p + 1 < KC) chunk(2 * p + 1, ys[1], false);
             }
         }
+        // Register i holds the count of bit 8(i/4) + 4h + i%4: the low bytes of
+        // registers u, 4+u, 8+u, 12+u go to bytes 0..3 of one dword, whose
+        // bits 0 then move to bits 8t + u.
         uint32_t word[kMfmaJC];
 #pragma unroll
         for (int jc = 0; jc < kMfmaJC; ++jc) {
+            uint32_t c[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) c[i] = (uint32_t)acc[jc][i];
             uint32_t mine = 0;
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                mine |= ((uint32_t)acc[jc][i] & 1u) << (8 * (i >> 2) + (i & 3));
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t lo = __builtin_amdgcn_perm(c[4 + u], c[u], 0x0c0c0400u);
+                const uint32_t hi = __builtin_amdgcn_perm(c[12 + u], c[8 + u], 0x04000c0cu);
+                mine |= ((lo | hi) & 0x01010101u) << u;
+            }
             mine <<= 4 * h;
             // lanes 0..31 (the ones that store) take the bits of lane + 32
             word[jc] = mine | __builtin_amdgcn_permlane32_swap(mine, mine, false, false)[1];
