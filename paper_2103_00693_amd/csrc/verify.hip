@@ -47,6 +47,136 @@ __global__ __launch_bounds__(256) void pair_stats_kernel(FactorIn f, const uint6
     }
 }
 
+// Membership on the matrix cores (n > 192, 1 <= n - r <= 128): the parities
+// <k_j, z_s> for all kernel vectors at once are the GF(2) product of the
+// strings (num x n) and the kernel basis transposed (n x (n - r)), computed
+// as in the sampler: v_mfma_scale_f32_32x32x64_f8f6f4 with E2M1 operands
+// whose set-bit products are exactly 1, fp32 sums that are integer counts,
+// bit 0 their parity.  K chunk w is string word w; lane half h takes its
+// 32-bit half, and nibble t of operand dword d stands for bit 4t + d of it.
+// The kernel vectors are already rows of n bits, the layout the basis operand
+// needs (lane = kernel vector), so they are encoded once into LDS without a
+// transpose.  A workgroup holds all (up to 128) of them; its 16 waves take
+// contiguous blocks of 32 strings.  The product is taken with the kernel
+// operand first, so accumulator register i of lane l holds the parity of
+// kernel vector 8(i/4) + 4(l/32) + i%4 of its 32-chunk for string l % 32.
+constexpr int kMemMfmaMinWords = 4;
+constexpr int kMemMfmaMaxVectors = 128;
+constexpr int kMemWaves = 16;
+
+typedef int m4i __attribute__((ext_vector_type(4)));
+typedef int m8i __attribute__((ext_vector_type(8)));
+typedef float m16f __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(64 * kMemWaves) void membership_mfma_kernel(
+    FactorIn f, const uint64_t *__restrict__ kernel, const uint64_t *__restrict__ z, uint64_t num,
+    uint8_t *__restrict__ member) {
+    constexpr int JC = kMemMfmaMaxVectors / 32;
+    __shared__ __align__(16) uint32_t Bop[(HLF_MAX_N / 64) * JC * 64 * 4];  // 64 KiB
+    __shared__ uint32_t target[JC];
+    if (*(volatile int32_t *)f.status != HLF_OK) return;
+    const int W = f.words;
+    const int nk = f.n - *f.rank;
+    if (nk < 1 || nk > kMemMfmaMaxVectors) return;  // the VALU kernel's case
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, m = lane & 31;
+    const int jcs = (nk + 31) >> 5;  // 32-vector chunks in use
+    if (tid < JC) target[tid] = 0;
+    __syncthreads();
+    // target bit j = <k_j, l> (mod 2)
+    if (tid < nk) {
+        uint64_t acc = 0;
+        for (int w = 0; w < W; ++w) acc ^= kernel[(size_t)tid * W + w] & f.shift[w];
+        if (__builtin_popcountll(acc) & 1) atomicOr(&target[tid >> 5], 1u << (tid & 31));
+    }
+    // Kernel operand of chunk (w, jc): lane (h, n), dword d, nibble t holds
+    // bit 64w + 32h + 4t + d of k_{32jc+n} at nibble position 2, 1, 0, 0 for
+    // d = 0, 1, 2, 3 (0 beyond n - r).
+    for (int t = wave; t < W * jcs; t += kMemWaves) {
+        const int w = t / jcs, jc = t - w * jcs;
+        const int j = 32 * jc + m;
+        const uint32_t y = j < nk ? (uint32_t)(kernel[(size_t)j * W + w] >> (32 * h)) : 0u;
+        uint32_t *dst = &Bop[((size_t)(w * JC + jc) * 64 + lane) * 4];
+        dst[0] = (y & 0x11111111u) << 2;
+        dst[1] = y & 0x22222222u;
+        dst[2] = (y & 0x44444444u) >> 2;
+        dst[3] = (y & 0x88888888u) >> 3;
+    }
+    __syncthreads();
+    uint32_t valid[JC], tgt[JC];
+#pragma unroll
+    for (int jc = 0; jc < JC; ++jc) {
+        const int left = nk - 32 * jc;
+        valid[jc] = left >= 32 ? ~0u : left > 0 ? (1u << left) - 1u : 0u;
+        tgt[jc] = target[jc];
+    }
+    const uint64_t nblk = (num + 31) >> 5;
+    const uint64_t per_wg = (nblk + gridDim.x - 1) / gridDim.x;
+    const uint64_t blk_end = min(nblk, (uint64_t)(blockIdx.x + 1) * per_wg);
+    for (uint64_t blk = (uint64_t)blockIdx.x * per_wg + wave; blk < blk_end; blk += kMemWaves) {
+        const uint64_t s = 32ull * blk + (uint64_t)m;  // this lane's string
+        const bool live = s < num;
+        // Lane half h loads words 2p + h of its string, all at once; one swap
+        // of the upper 32 lanes of a word's low dword with the lower 32 lanes
+        // of its high dword then leaves every lane the 32-bit half h of words
+        // 2p and 2p + 1 (lanes m and m + 32 hold the same string).
+        uint64_t zw[HLF_MAX_N / 128];
+#pragma unroll
+        for (int p = 0; p < HLF_MAX_N / 128; ++p) {
+            const int w = 2 * p + h;
+            zw[p] = (live && w < W) ? z[s * (uint64_t)W + (uint64_t)w] : 0ull;
+        }
+        m16f acc[JC];
+        auto chunk = [&](int w, uint32_t y) {
+            const m8i a = {(int)(y & 0x11111111u), (int)(y & 0x22222222u),
+                           (int)(y & 0x44444444u), (int)((y >> 1) & 0x44444444u), 0, 0, 0, 0};
+#pragma unroll
+            for (int jc = 0; jc < JC; ++jc) {
+                if (jc < jcs) {
+                    const m4i b4 = *reinterpret_cast<const m4i *>(&Bop[((size_t)(w * JC + jc) * 64 + lane) * 4]);
+                    const m8i b = {b4[0], b4[1], b4[2], b4[3], 0, 0, 0, 0};
+                    acc[jc] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        b, a, w == 0 ? m16f{} : acc[jc], 4, 4, 0, 127, 0, 127);
+                }
+            }
+        };
+#pragma unroll
+        for (int p = 0; p < HLF_MAX_N / 128; ++p) {
+            if (2 * p < W) {
+                const auto ys = __builtin_amdgcn_permlane32_swap((uint32_t)zw[p], (uint32_t)(zw[p] >> 32),
+                                                                 false, false);
+                chunk(2 * p, ys[0]);
+                if (2 * p + 1 < W) chunk(2 * p + 1, ys[1]);
+            }
+        }
+        // Register i holds the count of vector 8(i/4) + 4h + i%4: the low bytes
+        // of registers u, 4+u, 8+u, 12+u go to bytes 0..3 of one dword, whose
+        // bits 0 then move to bits 8t + u; lanes 0..31 take the other 16 bits
+        // from lane + 32.
+        uint32_t bad = 0;
+#pragma unroll
+        for (int jc = 0; jc < JC; ++jc) {
+            if (jc < jcs) {
+                uint32_t c[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) c[i] = (uint32_t)acc[jc][i];
+                uint32_t mine = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t lo = __builtin_amdgcn_perm(c[4 + u], c[u], 0x0c0c0400u);
+                    const uint32_t hi = __builtin_amdgcn_perm(c[12 + u], c[8 + u], 0x04000c0cu);
+                    mine |= ((lo | hi) & 0x01010101u) << u;
+                }
+                mine <<= 4 * h;
+                const uint32_t word = mine | __builtin_amdgcn_permlane32_swap(mine, mine, false, false)[1];
+                bad |= (word ^ tgt[jc]) & valid[jc];
+            }
+        }
+        const uint64_t so = 32ull * blk + (uint64_t)lane;  // string `lane` for lanes < 32
+        if (lane < 32 && so < num) member[so] = bad ? 0 : 1;
+    }
+}
+
 // One thread per string: member[s] = 1 iff <k_j, z_s> = <k_j, l> (mod 2) for
 // every kernel vector k_j, j < n - r.  <k_j, l> = l_{f_j} because k_j is 1 at
 // its free column f_j, 0 at the other free columns, and l is 0 on the pivots.
@@ -60,6 +190,7 @@ __global__ __launch_bounds__(256) void membership_kernel(FactorIn f, const uint6
     if (*(volatile int32_t *)f.status != HLF_OK) return;
     const int n = f.n;
     const int nk = n - *f.rank;
+    if (W >= kMemMfmaMinWords && nk >= 1 && nk <= kMemMfmaMaxVectors) return;  // matrix-core kernel
     __shared__ uint32_t target[HLF_MAX_N / 32];
     for (int t = threadIdx.x; t < HLF_MAX_N / 32; t += blockDim.x) target[t] = 0;
     __syncthreads();
@@ -134,6 +265,19 @@ hlf_status launch_pair_stats(const FactorIn &f, const uint64_t *rows, uint8_t *q
 
 hlf_status launch_membership(const FactorIn &f, const uint64_t *kernel, const uint64_t *z,
                              uint64_t num, uint8_t *member, hipStream_t stream) {
+    // n - r is on the device: for n > 192 both kernels are launched and each
+    // returns at once unless the case is its own (1 <= n - r <= 128 for the
+    // matrix cores, every other one for the VALU kernel).
+    if (f.words >= kMemMfmaMinWords) {
+        const uint64_t blocks32 = (num + 31) / 32;
+        uint64_t g = (uint64_t)device_cu_count();
+        const uint64_t most = (blocks32 + kMemWaves - 1) / kMemWaves;
+        if (g > most) g = most;
+        if (g == 0) g = 1;
+        hipLaunchKernelGGL(membership_mfma_kernel, dim3((unsigned)g), dim3(64 * kMemWaves), 0, stream,
+                           f, kernel, z, num, member);
+        if (hipGetLastError() != hipSuccess) return HLF_EDEVICE;
+    }
     return launch_membership_w(f.words, f, kernel, z, num, member, stream,
                                std::make_integer_sequence<int, HLF_MAX_N / 64>{});
 }

@@ -234,6 +234,56 @@ def test_membership_n1024_samples_flips_and_xeb():
     assert int(hlf.membership(F, moved).sum().item()) == 20000
 
 
+
+def _embedded_sym(n, m, seed):
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(n, size=m, replace=False))
+    A = np.zeros((n, n), dtype=np.uint8)
+    A[np.ix_(idx, idx)] = random_symmetric(m, seed, density=0.3)
+    return A
+
+
+MEMBERSHIP_CASES = {  # n - r of each instance: one to four 32-vector chunks, beyond 128, none
+    "nk21": lambda: _embedded_sym(256, 236, 1),
+    "nk51": lambda: _embedded_sym(256, 206, 2),
+    "nk80": lambda: _embedded_sym(320, 240, 3),
+    "nk120": lambda: _embedded_sym(256, 136, 4),
+    "nk157": lambda: _embedded_sym(256, 100, 5),
+    "nk2": lambda: random_symmetric(256, 6, density=0.5),
+    "nk0": lambda: random_symmetric(200, 8, density=0.5),
+}
+
+
+@pytest.mark.parametrize("name", list(MEMBERSHIP_CASES))
+def test_membership_n_above_192_against_definition(name):
+    # n > 192: the matrix-core kernel for 1 <= n - r <= 128, the per-string
+    # kernel otherwise.  Exact samples, samples with one or two flipped bits
+    # and uniform strings, each compared with the definition: z is a solution
+    # iff <k_f, z> = q(k_f)/2 (mod 2) for every kernel vector k_f.
+    A = MEMBERSHIP_CASES[name]()
+    n = A.shape[0]
+    Fo = O.factor(A)
+    ker = Fo["kernel"]
+    print(f"[verify] membership {name}: n={n} n-r={len(ker)}", flush=True)
+    F, st = gpu_factor(A)
+    assert st == hlf.HLF_OK
+    rng = np.random.default_rng(len(ker) + 7)
+    members = O.sample(Fo, 3, 200)
+    flipped = [z ^ (1 << int(rng.integers(n))) for z in members[:100]]
+    flipped += [z ^ (1 << int(rng.integers(n))) ^ (1 << int(rng.integers(n))) for z in members[100:]]
+    uniform = [int.from_bytes(rng.bytes((n + 7) // 8), "little") & ((1 << n) - 1) for _ in range(100)]
+    zs = members + flipped + uniform + members[:37]  # 637 strings: a ragged last block
+    qhalf = [(O.q_form(A, O.bits_to_array(k, n)) // 2) & 1 for k in ker]
+    want = [all(bin(z & k).count("1") % 2 == q for k, q in zip(ker, qhalf)) for z in zs]
+    for z, w in list(zip(zs, want))[::97]:  # the restated definition agrees with the oracle's own
+        assert O.is_solution(A, z, kernel=ker) == w
+    W = (n + 63) // 64
+    words = np.array([[(z >> (64 * w)) & ((1 << 64) - 1) for w in range(W)] for z in zs],
+                     dtype=np.uint64).view(np.int64)
+    m = hlf.membership(F, torch.from_numpy(words).to("cuda")).cpu().numpy()
+    assert [bool(v) for v in m] == want
+    assert all(want[:200])
+
 def test_membership_requires_kernel_buffer():
     A = grid_instance(3, seed=1)
     F, _ = gpu_factor(A, kernel=False)
