@@ -83,7 +83,7 @@ __device__ int factor_wave_core(int n, int W, bool bad_input, const FactorOut &o
 
     uint64_t row[WMAX][WMAX];
     bool used[WMAX];
-    int rk[WMAX];
+    int rk[WMAX], pc[WMAX];  // rank and pivot column of a pivot row
 #pragma unroll
     for (int s = 0; s < WMAX; ++s) {
         const int i = s * 64 + lane;
@@ -91,6 +91,7 @@ __device__ int factor_wave_core(int n, int W, bool bad_input, const FactorOut &o
         for (int w = 0; w < WMAX; ++w) row[s][w] = (i < n && w < W) ? sm.orig[i * W + w] : 0ull;
         used[s] = false;
         rk[s] = -1;
+        pc[s] = -1;
     }
 
     // Validation: pad bits zero, A = A^T (slot s of word cw, transposed across
@@ -163,64 +164,106 @@ __device__ int factor_wave_core(int n, int W, bool bad_input, const FactorOut &o
                 if (is_p) {
                     used[s] = true;
                     rk[s] = r;
+                    pc[s] = c;
                 }
             }
             if (lane == 0) sm.piv[r] = c;
             ++r;
         }
     }
-#pragma unroll
-    for (int s = 0; s < WMAX; ++s)
-        if (used[s])
-#pragma unroll
-            for (int w = 0; w < WMAX; ++w)
-                if (w < W) sm.rref[rk[s] * W + w] = row[s][w];
-    wave_lds_sync();
-
-    for (int k = lane; k < n; k += 64) out.pivots[k] = (k < r) ? sm.piv[k] : -1;
-    for (int idx = lane; idx < r * W; idx += 64) {
-        const int k = idx / W, w = idx - k * W;
-        out.basis[idx] = sm.orig[sm.piv[k] * W + w];
-    }
-
-    // Kernel vectors k_f and q(k_f) = sum_{i in supp k_f} popcount(A_i & k_f).
-    const int nk = n - r;
-    for (int j = lane; j < nk; j += 64) {
-        const int f = sm.freec[j];
-        uint64_t kv[WMAX];
-#pragma unroll
-        for (int w = 0; w < WMAX; ++w) kv[w] = 0;
-        set_bit<WMAX>(kv, f);
-        for (int k = 0; k < r; ++k) {
-            if ((sm.rref[k * W + (f >> 6)] >> (f & 63)) & 1ull) set_bit<WMAX>(kv, sm.piv[k]);
+    if constexpr (WMAX == 1) {
+        // One word per row (n <= 64).  P[c] = the reduced pivot row whose
+        // pivot column is c, 0 at free columns; transposed across the wave,
+        // lane f holds column f of P, whose bit c is that row's entry f, so
+        // k_f = e_f | column f of P for a free column f.
+        sm.rref[lane] = 0ull;
+        wave_lds_sync();
+        if (used[0]) sm.rref[pc[0]] = row[0][0];
+        wave_lds_sync();
+        const uint64_t P = sm.rref[lane];
+        if (lane < n) out.pivots[lane] = (lane < r) ? sm.piv[lane] : -1;
+        if (lane < r) out.basis[lane] = sm.orig[sm.piv[lane]];
+        const uint64_t pivmask = __ballot(P != 0ull);  // a pivot row is never 0
+        const uint64_t freemask = __ballot(lane < n) & ~pivmask;
+        const bool is_free = (freemask >> lane) & 1ull;
+        const uint64_t T = wave_transpose64(P);  // every lane takes part in the exchanges
+        const uint64_t kv = is_free ? (T | (1ull << lane)) : 0ull;
+        if (out.kernel && is_free) out.kernel[__builtin_popcountll(freemask & ((1ull << lane) - 1ull))] = kv;
+        // q(k_f) = sum over i in supp k_f of popcount(A_i & k_f), one uniform
+        // step per free column: every term is even (A k_f = 0 mod 2), so bit
+        // 1 of the sum is the parity of the terms = 2 mod 4.
+        const uint64_t Ai = lane < n ? sm.orig[lane] : 0ull;
+        uint64_t shiftbits = 0ull;
+        bool internal = false;
+        for (uint64_t fm = freemask; fm; fm &= fm - 1ull) {
+            const int f = __builtin_ctzll(fm);
+            const uint64_t x = readlane64(kv, f);
+            const uint32_t term = ((x >> lane) & 1ull) ? (uint32_t)__builtin_popcountll(Ai & x) : 0u;
+            if (__ballot(term & 1u)) internal = true;
+            if (__builtin_popcountll(__ballot(term & 2u)) & 1) shiftbits |= 1ull << f;
         }
-        if (out.kernel)
+        if (lane == 0) sm.shiftw[0] = shiftbits;
+        wave_lds_sync();
+        if (lane == 0) {
+            out.shift[0] = shiftbits;
+            *out.rank = r;
+            *out.status = internal ? HLF_EINTERNAL : HLF_OK;
+        }
+        return internal ? -1 : r;
+    } else {
 #pragma unroll
-            for (int w = 0; w < WMAX; ++w)
-                if (w < W) out.kernel[j * W + w] = kv[w];
-        uint32_t q = 0;
-#pragma unroll
-        for (int iw = 0; iw < WMAX; ++iw) {
-            uint64_t bits = kv[iw];
-            while (bits) {
-                const int i = iw * 64 + __builtin_ctzll(bits);
-                bits &= bits - 1;
+        for (int s = 0; s < WMAX; ++s)
+            if (used[s])
 #pragma unroll
                 for (int w = 0; w < WMAX; ++w)
-                    if (w < W) q += __builtin_popcountll(sm.orig[i * W + w] & kv[w]);
-            }
+                    if (w < W) sm.rref[rk[s] * W + w] = row[s][w];
+        wave_lds_sync();
+
+        for (int k = lane; k < n; k += 64) out.pivots[k] = (k < r) ? sm.piv[k] : -1;
+        for (int idx = lane; idx < r * W; idx += 64) {
+            const int k = idx / W, w = idx - k * W;
+            out.basis[idx] = sm.orig[sm.piv[k] * W + w];
         }
-        if (q & 1u) sm.internal = 1;
-        if (q & 2u) atomicOr(&sm.shiftw[f >> 6], 1ull << (f & 63));
+
+        // Kernel vectors k_f and q(k_f) = sum_{i in supp k_f} popcount(A_i & k_f).
+        const int nk = n - r;
+        for (int j = lane; j < nk; j += 64) {
+            const int f = sm.freec[j];
+            uint64_t kv[WMAX];
+#pragma unroll
+            for (int w = 0; w < WMAX; ++w) kv[w] = 0;
+            set_bit<WMAX>(kv, f);
+            for (int k = 0; k < r; ++k) {
+                if ((sm.rref[k * W + (f >> 6)] >> (f & 63)) & 1ull) set_bit<WMAX>(kv, sm.piv[k]);
+            }
+            if (out.kernel)
+#pragma unroll
+                for (int w = 0; w < WMAX; ++w)
+                    if (w < W) out.kernel[j * W + w] = kv[w];
+            uint32_t q = 0;
+#pragma unroll
+            for (int iw = 0; iw < WMAX; ++iw) {
+                uint64_t bits = kv[iw];
+                while (bits) {
+                    const int i = iw * 64 + __builtin_ctzll(bits);
+                    bits &= bits - 1;
+#pragma unroll
+                    for (int w = 0; w < WMAX; ++w)
+                        if (w < W) q += __builtin_popcountll(sm.orig[i * W + w] & kv[w]);
+                }
+            }
+            if (q & 1u) sm.internal = 1;
+            if (q & 2u) atomicOr(&sm.shiftw[f >> 6], 1ull << (f & 63));
+        }
+        wave_lds_sync();
+        if (lane < W) out.shift[lane] = sm.shiftw[lane];
+        const bool internal = sm.internal != 0;
+        if (lane == 0) {
+            *out.rank = r;
+            *out.status = internal ? HLF_EINTERNAL : HLF_OK;
+        }
+        return internal ? -1 : r;
     }
-    wave_lds_sync();
-    if (lane < W) out.shift[lane] = sm.shiftw[lane];
-    const bool internal = sm.internal != 0;
-    if (lane == 0) {
-        *out.rank = r;
-        *out.status = internal ? HLF_EINTERNAL : HLF_OK;
-    }
-    return internal ? -1 : r;
 }
 
 }  // namespace hlf
