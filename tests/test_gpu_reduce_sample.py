@@ -211,14 +211,16 @@ def test_sample_uniformity():
 
 
 @pytest.mark.parametrize("name,A,num", [
+    ("grid N=12 (W=3)", grid_instance(12, p=0.5, seed=5), 777),
+    ("random n=100 (W=2)", random_symmetric(100, 11, 0.3), 500),
     ("grid N=25 (W=10)", grid_instance(25, p=0.5, seed=12), 1000),
     ("random n=1024 (r=1024)", random_symmetric(1024, 8, 0.5), 333),
     ("grid N=32 all edges", grid_instance(32, p=1.0, seed=2), 129),
 ])
 def test_sample_large_n_matrix_core_path(name, A, num):
-    """n > 192 runs on the matrix cores (int8 products, bit 0 of the sums):
-    exact words against the oracle for the SplitMix64 stream and for explicit
-    coefficients, with sample counts that leave ragged passes."""
+    """n > 64 runs on the matrix cores (fp4 products, bit 0 of the fp32
+    counts): exact words against the oracle for the SplitMix64 stream and for
+    explicit coefficients, with sample counts that leave ragged blocks."""
     Fo = O.factor(A)
     F, st = gpu_factor(A)
     r, W = Fo["rank"], Fo["words"]
@@ -244,6 +246,8 @@ def _one_edge(n, i, j, diag=()):
 
 
 @pytest.mark.parametrize("name,A", [
+    ("zero n=100 (r=0)", np.zeros((100, 100), dtype=np.uint8)),
+    ("one edge n=129 (r=2)", _one_edge(129, 3, 128)),
     ("zero n=300 (r=0)", np.zeros((300, 300), dtype=np.uint8)),
     ("one edge n=300 (r=2)", _one_edge(300, 5, 290)),
     ("one loop n=257 (r=1)", _one_edge(257, 256, 256)),
