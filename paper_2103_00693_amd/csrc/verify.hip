@@ -47,6 +47,81 @@ __global__ __launch_bounds__(256) void pair_stats_kernel(FactorIn f, const uint6
     }
 }
 
+typedef int m4i __attribute__((ext_vector_type(4)));
+typedef int m8i __attribute__((ext_vector_type(8)));
+typedef float m16f __attribute__((ext_vector_type(16)));
+
+// Pair statistics on the matrix cores (n > 64): quarters[i][j] needs |A_i|,
+// |A_j| and the integer dot product popcount(A_i & A_j) (rows equal exactly
+// when all three agree), and the dot products of all row pairs are the
+// product of the packed rows with their transpose.  One wave per 32 x 32 tile
+// of (i, j): v_mfma_scale_f32_32x32x64_f8f6f4 with E2M1 operands whose
+// set-bit products are exactly 1 (the i rows at nibble positions 2, 1, 0, 0,
+// the j rows at 0, 1, 2, 2 for bits 4t + 0..3), so the fp32 sums are the
+// counts.  K chunk w is row word w; lane half h takes its 32-bit half.
+// Accumulator register q of lane l holds the count of rows i = 32bi + 8(q/4)
+// + 4(l/32) + q%4 and j = 32bj + l%32.
+constexpr int kPairWaves = 4;
+
+__global__ __launch_bounds__(64 * kPairWaves) void pair_stats_mfma_kernel(
+    FactorIn f, const uint64_t *__restrict__ rows, uint8_t *__restrict__ quarters) {
+    __shared__ uint32_t pci[kPairWaves][32];
+    if (*(volatile int32_t *)f.status != HLF_OK) return;
+    const int n = f.n, W = f.words;
+    const int nb = (n + 31) >> 5;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, m = lane & 31;
+    const int t = blockIdx.x * kPairWaves + wave;  // tile index, wave-uniform
+    if (t >= nb * nb) return;                      // no barrier below
+    const int bi = t / nb, bj = t - bi * nb;
+    const int i = 32 * bi + m, j = 32 * bj + m;    // this lane's rows
+    // words 2p + h of rows i and j, all loads at once
+    uint64_t xi[HLF_MAX_N / 128], xj[HLF_MAX_N / 128];
+    uint32_t pi = 0, pj = 0;
+#pragma unroll
+    for (int p = 0; p < HLF_MAX_N / 128; ++p) {
+        const int w = 2 * p + h;
+        xi[p] = (i < n && w < W) ? rows[(size_t)i * W + w] : 0ull;
+        xj[p] = (j < n && w < W) ? rows[(size_t)j * W + w] : 0ull;
+        pi += (uint32_t)__builtin_popcountll(xi[p]);
+        pj += (uint32_t)__builtin_popcountll(xj[p]);
+    }
+    // whole-row popcounts: add the other half's words (lane l ^ 32)
+    pi += __builtin_amdgcn_permlane32_swap(pi, pi, false, false)[h ? 0 : 1];
+    pj += __builtin_amdgcn_permlane32_swap(pj, pj, false, false)[h ? 0 : 1];
+    if (lane < 32) pci[wave][m] = pi;
+    m16f acc;
+    auto chunk = [&](int w, uint32_t yi, uint32_t yj) {
+        const m8i a = {(int)((yi & 0x11111111u) << 2), (int)(yi & 0x22222222u),
+                       (int)((yi & 0x44444444u) >> 2), (int)((yi & 0x88888888u) >> 3), 0, 0, 0, 0};
+        const m8i b = {(int)(yj & 0x11111111u), (int)(yj & 0x22222222u),
+                       (int)(yj & 0x44444444u), (int)((yj >> 1) & 0x44444444u), 0, 0, 0, 0};
+        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, w == 0 ? m16f{} : acc, 4, 4, 0, 127,
+                                                             0, 127);
+    };
+#pragma unroll
+    for (int p = 0; p < HLF_MAX_N / 128; ++p) {
+        if (2 * p < W) {
+            const auto yi = __builtin_amdgcn_permlane32_swap((uint32_t)xi[p], (uint32_t)(xi[p] >> 32), false, false);
+            const auto yj = __builtin_amdgcn_permlane32_swap((uint32_t)xj[p], (uint32_t)(xj[p] >> 32), false, false);
+            chunk(2 * p, yi[0], yj[0]);
+            if (2 * p + 1 < W) chunk(2 * p + 1, yi[1], yj[1]);
+        }
+    }
+    wave_lds_sync();  // pci of this wave written above
+    if (j < n) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int mi = 8 * (q >> 2) + 4 * h + (q & 3);
+            const int ii = 32 * bi + mi;
+            if (ii < n) {
+                const uint32_t c = (uint32_t)acc[q], ni = pci[wave][mi];
+                quarters[(size_t)ii * n + j] = (ni == 0u || pj == 0u) ? 0 : (ni == pj && c == ni) ? 2 : 1;
+            }
+        }
+    }
+}
+
 // Membership on the matrix cores (n > 192, 1 <= n - r <= 128): the parities
 // <k_j, z_s> for all kernel vectors at once are the GF(2) product of the
 // strings (num x n) and the kernel basis transposed (n x (n - r)), computed
@@ -64,9 +139,6 @@ constexpr int kMemMfmaMinWords = 4;
 constexpr int kMemMfmaMaxVectors = 128;
 constexpr int kMemWaves = 16;
 
-typedef int m4i __attribute__((ext_vector_type(4)));
-typedef int m8i __attribute__((ext_vector_type(8)));
-typedef float m16f __attribute__((ext_vector_type(16)));
 
 __global__ __launch_bounds__(64 * kMemWaves) void membership_mfma_kernel(
     FactorIn f, const uint64_t *__restrict__ kernel, const uint64_t *__restrict__ z, uint64_t num,
@@ -256,11 +328,14 @@ hlf_status launch_membership_w(int W, const FactorIn &f, const uint64_t *kernel,
 hlf_status launch_pair_stats(const FactorIn &f, const uint64_t *rows, uint8_t *quarters,
                              hipStream_t stream) {
     const int W = f.words;
-    if (W <= 1) return launch_pair_stats_t<1>(f, rows, quarters, stream);
-    if (W <= 2) return launch_pair_stats_t<2>(f, rows, quarters, stream);
-    if (W <= 4) return launch_pair_stats_t<4>(f, rows, quarters, stream);
-    if (W <= 8) return launch_pair_stats_t<8>(f, rows, quarters, stream);
-    return launch_pair_stats_t<16>(f, rows, quarters, stream);
+    if (W >= 2) {
+        const int nb = (f.n + 31) / 32;
+        const unsigned blocks = (unsigned)((nb * nb + kPairWaves - 1) / kPairWaves);
+        hipLaunchKernelGGL(pair_stats_mfma_kernel, dim3(blocks), dim3(64 * kPairWaves), 0, stream, f,
+                           rows, quarters);
+        return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
+    }
+    return launch_pair_stats_t<1>(f, rows, quarters, stream);
 }
 
 hlf_status launch_membership(const FactorIn &f, const uint64_t *kernel, const uint64_t *z,
