@@ -47,6 +47,94 @@ __device__ __forceinline__ bool tile_pair_asym(uint64_t x, uint64_t y) {
     return __ballot(wave_transpose64(x) != y) != 0;
 }
 
+// A0 for n > 64 with n a multiple of 16 and A 16-byte aligned: two launches.
+// pack_rows_kernel packs 16 rows per workgroup (16-byte loads, gather4) and
+// checks that every byte is 0 or 1.  gather4 is only meaningful on 0/1 bytes,
+// so a row holding another value packs to arbitrary bits; the workgroup then
+// makes the packed matrix asymmetric inside one of its own row pairs (i, i^1)
+// whatever those bits are: if one row of the pair is bad, its entry towards
+// the other becomes the complement of the other's entry back, if both are,
+// the two entries become 1 and 0.  pack_check_kernel checks A = A^T on the
+// packed rows, tile pair by tile pair, and is the only writer of the status.
+constexpr int kPackRowsPerBlock = 16;
+constexpr int kPackRowsThreads = 256;
+
+__global__ __launch_bounds__(kPackRowsThreads) void pack_rows_kernel(const uint8_t *__restrict__ A,
+                                                                     int n, int W,
+                                                                     uint64_t *__restrict__ rows) {
+    __shared__ uint64_t lds[kPackRowsPerBlock * HLF_MAX_WORDS];
+    __shared__ int badrow[kPackRowsPerBlock];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * kPackRowsPerBlock;
+    const int cpr = n >> 4;  // 16-byte chunks per row
+    if (tid < kPackRowsPerBlock) badrow[tid] = 0;
+    for (int idx = tid; idx < kPackRowsPerBlock * W; idx += kPackRowsThreads) lds[idx] = 0;
+    __syncthreads();
+    uint16_t *l16 = reinterpret_cast<uint16_t *>(lds);
+    const u32x4 *A16 = reinterpret_cast<const u32x4 *>(A);
+    // at most 16 rows x 64 chunks = 4 chunks per thread, all loads first
+    constexpr int kPer = kPackRowsPerBlock * (HLF_MAX_N / 16) / kPackRowsThreads;
+    u32x4 v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int idx = tid + k * kPackRowsThreads;
+        const int lr = idx / cpr, c = idx - lr * cpr;
+        const bool ok = lr < kPackRowsPerBlock && i0 + lr < n;
+        v[k] = ok ? __builtin_nontemporal_load(&A16[(size_t)(i0 + lr) * cpr + c]) : u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int idx = tid + k * kPackRowsThreads;
+        const int lr = idx / cpr, c = idx - lr * cpr;
+        if (lr < kPackRowsPerBlock && i0 + lr < n) {
+            if (((v[k].x | v[k].y | v[k].z | v[k].w) & 0xFEFEFEFEu) != 0u) badrow[lr] = 1;
+            l16[lr * 4 * W + c] = (uint16_t)(gather4(v[k].x) | (gather4(v[k].y) << 4) |
+                                             (gather4(v[k].z) << 8) | (gather4(v[k].w) << 12));
+        }
+    }
+    __syncthreads();
+    if (tid < kPackRowsPerBlock / 2) {  // row pair (a, a + 1); n % 16 == 0, so both exist
+        const int a = 2 * tid, b = a + 1, ia = i0 + a, ib = i0 + b;
+        if (ib < n && (badrow[a] || badrow[b])) {
+            uint64_t &ab = lds[a * W + (ib >> 6)];  // holds entry (ia, ib)
+            uint64_t &ba = lds[b * W + (ia >> 6)];  // holds entry (ib, ia)
+            const uint64_t mab = 1ull << (ib & 63), mba = 1ull << (ia & 63);
+            if (badrow[a] && badrow[b]) {
+                ab |= mab;
+                ba &= ~mba;
+            } else if (badrow[a]) {
+                ab = (ba & mba) ? (ab & ~mab) : (ab | mab);
+            } else {
+                ba = (ab & mab) ? (ba & ~mba) : (ba | mba);
+            }
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < kPackRowsPerBlock * W; idx += kPackRowsThreads) {
+        const int lr = idx / W, w = idx - lr * W;
+        const int i = i0 + lr;
+        if (i < n) rows[(size_t)i * W + w] = lds[lr * W + w];
+    }
+}
+
+__global__ __launch_bounds__(1024) void pack_check_kernel(const uint64_t *__restrict__ rows, int n,
+                                                          int W, int32_t *__restrict__ status) {
+    __shared__ int bad;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int t = wave; t < W * W; t += nwaves) {  // wave-uniform
+        const int I = t / W, J = t - I * W;
+        if (J < I) continue;
+        const int ri = 64 * I + lane, rj = 64 * J + lane;
+        const uint64_t x = ri < n ? rows[(size_t)ri * W + J] : 0ull;
+        const uint64_t y = rj < n ? rows[(size_t)rj * W + I] : 0ull;
+        if (tile_pair_asym(x, y) && lane == 0) bad = 1;
+    }
+    __syncthreads();
+    if (tid == 0) *status = bad ? HLF_ENOTSYM : HLF_OK;
+}
+
 template <int WMAX>
 __global__ __launch_bounds__(64 * WMAX) void pack_dense_kernel(const uint8_t *__restrict__ A, int n,
                                                                int W, uint64_t *__restrict__ rows,
@@ -516,6 +604,14 @@ hlf_status launch_workgroup_t(const uint64_t *rows, int n, int W, const FactorOu
 
 hlf_status launch_pack(const uint8_t *A, int n, int W, uint64_t *rows, int32_t *status,
                        hipStream_t stream) {
+    if (W >= 2 && (n & 15) == 0 && ((uintptr_t)A & 15u) == 0) {
+        const unsigned blocks = (unsigned)((n + kPackRowsPerBlock - 1) / kPackRowsPerBlock);
+        hipLaunchKernelGGL(pack_rows_kernel, dim3(blocks), dim3(kPackRowsThreads), 0, stream, A, n, W,
+                           rows);
+        if (hipGetLastError() != hipSuccess) return HLF_EDEVICE;
+        hipLaunchKernelGGL(pack_check_kernel, dim3(1), dim3(1024), 0, stream, rows, n, W, status);
+        return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
+    }
     if (W <= 1) return launch_pack_t<1>(A, n, W, rows, status, stream);
     if (W <= 2) return launch_pack_t<2>(A, n, W, rows, status, stream);
     if (W <= 3) return launch_pack_t<3>(A, n, W, rows, status, stream);

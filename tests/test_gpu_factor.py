@@ -106,7 +106,7 @@ def test_factor_large_workgroup(name, A):
     assert_record_matches(F, ref, name)
 
 
-@pytest.mark.parametrize("n", [5, 64, 100, 300, 1024])
+@pytest.mark.parametrize("n", [5, 64, 100, 128, 256, 300, 320, 1008, 1024])
 def test_pack_matches_layout(n):
     print(f"[pack] n={n}", flush=True)
     A = random_symmetric(n, 77 + n, 0.4)
@@ -116,7 +116,7 @@ def test_pack_matches_layout(n):
     assert np.array_equal(hlf.as_uint64(rows), oracle_rows(A))
 
 
-@pytest.mark.parametrize("n", [4, 65, 200, 1024])
+@pytest.mark.parametrize("n", [4, 65, 128, 200, 256, 1008, 1024])
 def test_pack_rejects_asymmetric_and_non_binary(n):
     print(f"[pack-invalid] n={n}", flush=True)
     A = random_symmetric(n, 5, 0.5)
@@ -127,6 +127,24 @@ def test_pack_rejects_asymmetric_and_non_binary(n):
     B[n // 2, n // 2] = 2  # not 0/1
     _, st = hlf.pack_dense(device_matrix(B))
     assert int(st.item()) == hlf.HLF_ENOTSYM
+
+
+@pytest.mark.parametrize("n", [128, 1008])
+def test_pack_non_binary_rows_anywhere(n):
+    # n > 64 and a multiple of 16 packs rows across workgroups: a byte other
+    # than 0 and 1 in any row, alone or in adjacent rows, must give ENOTSYM,
+    # and a valid matrix right after must give OK again.
+    A = random_symmetric(n, 21, 0.5)
+    for rows_bad in ([0], [n - 1], [5, 6], [n - 2, n - 1, 0]):
+        B = A.copy()
+        for i in rows_bad:
+            B[i, (3 * i + 1) % n] = 255
+        print(f"[pack-invalid] n={n} rows={rows_bad}", flush=True)
+        _, st = hlf.pack_dense(device_matrix(B))
+        assert int(st.item()) == hlf.HLF_ENOTSYM, rows_bad
+        rows, st = hlf.pack_dense(device_matrix(A))
+        assert int(st.item()) == hlf.HLF_OK
+        assert np.array_equal(hlf.as_uint64(rows), oracle_rows(A))
 
 
 @pytest.mark.parametrize("workgroup", [False, True])
