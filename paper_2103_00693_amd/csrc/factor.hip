@@ -47,20 +47,24 @@ __device__ __forceinline__ bool tile_pair_asym(uint64_t x, uint64_t y) {
     return __ballot(wave_transpose64(x) != y) != 0;
 }
 
-// A0 for n > 64 with n a multiple of 16 and A 16-byte aligned: two launches.
-// pack_rows_kernel packs 16 rows per workgroup (16-byte loads, gather4) and
-// checks that every byte is 0 or 1.  gather4 is only meaningful on 0/1 bytes,
-// so a row holding another value packs to arbitrary bits; the workgroup then
-// makes the packed matrix asymmetric inside one of its own row pairs (i, i^1)
-// whatever those bits are: if one row of the pair is bad, its entry towards
-// the other becomes the complement of the other's entry back, if both are,
-// the two entries become 1 and 0.  pack_check_kernel checks A = A^T on the
-// packed rows, tile pair by tile pair, and is the only writer of the status.
+// A0 for n > 64: two launches.  pack_rows_kernel packs 16 rows per
+// workgroup (16-byte loads and gather4 when n is a multiple of 16 and A is
+// 16-byte aligned, else byte loads and one ballot per row word) and checks
+// that every byte is 0 or 1.  gather4 is only meaningful on 0/1 bytes, so a
+// row holding another value may pack to arbitrary bits; the workgroup then
+// marks it so that the check below must fail whatever those bits are.  When
+// n is not a multiple of 64 the row gets pad bit 63 of its last word.  When
+// it is, every block is 16 full rows, and the asymmetry goes inside one of
+// the workgroup's own row pairs (i, i^1): if one row of the pair is bad, its
+// entry towards the other becomes the complement of the other's entry back,
+// if both are, the two entries become 1 and 0.  pack_check_kernel checks the
+// pad bits and A = A^T on the packed rows, tile pair by tile pair, and is the
+// only writer of the status.
 constexpr int kPackRowsPerBlock = 16;
 constexpr int kPackRowsThreads = 256;
 
 __global__ __launch_bounds__(kPackRowsThreads) void pack_rows_kernel(const uint8_t *__restrict__ A,
-                                                                     int n, int W,
+                                                                     int n, int W, int vec16,
                                                                      uint64_t *__restrict__ rows) {
     __shared__ uint64_t lds[kPackRowsPerBlock * HLF_MAX_WORDS];
     __shared__ int badrow[kPackRowsPerBlock];
@@ -70,6 +74,32 @@ __global__ __launch_bounds__(kPackRowsThreads) void pack_rows_kernel(const uint8
     if (tid < kPackRowsPerBlock) badrow[tid] = 0;
     for (int idx = tid; idx < kPackRowsPerBlock * W; idx += kPackRowsThreads) lds[idx] = 0;
     __syncthreads();
+    if (!vec16) {
+        // (row, word) items per wave: lane l loads byte 64w + l of the row, a
+        // ballot gives the packed word; eight items' loads go out together.
+        const int lane = tid & 63, wave = tid >> 6;
+        constexpr int kWaves = kPackRowsThreads / 64, kBatch = 8;
+        const int items = kPackRowsPerBlock * W;
+        for (int it0 = wave * kBatch; it0 < items; it0 += kWaves * kBatch) {
+            uint32_t byte[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int it = it0 + u, lr = it / W, w = it - lr * W;
+                const int i = i0 + lr, c = 64 * w + lane;
+                byte[u] = (it < items && i < n && c < n) ? (uint32_t)A[(size_t)i * n + c] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int it = it0 + u, lr = it / W;
+                const uint64_t word = __ballot(byte[u] & 1u);
+                const bool badb = __ballot(byte[u] > 1u) != 0;
+                if (lane == 0 && it < items) {
+                    lds[it] = word;  // it = lr * W + w
+                    if (badb) badrow[lr] = 1;
+                }
+            }
+        }
+    } else {
     uint16_t *l16 = reinterpret_cast<uint16_t *>(lds);
     const u32x4 *A16 = reinterpret_cast<const u32x4 *>(A);
     // at most 16 rows x 64 chunks = 4 chunks per thread, all loads first
@@ -92,8 +122,11 @@ __global__ __launch_bounds__(kPackRowsThreads) void pack_rows_kernel(const uint8
                                              (gather4(v[k].z) << 8) | (gather4(v[k].w) << 12));
         }
     }
+    }
     __syncthreads();
-    if (tid < kPackRowsPerBlock / 2) {  // row pair (a, a + 1); n % 16 == 0, so both exist
+    if ((n & 63) != 0) {  // pad bit 63 of the last word of a bad row
+        if (tid < kPackRowsPerBlock && i0 + tid < n && badrow[tid]) lds[tid * W + W - 1] |= 1ull << 63;
+    } else if (tid < kPackRowsPerBlock / 2) {  // row pair (a, a + 1): full blocks
         const int a = 2 * tid, b = a + 1, ia = i0 + a, ib = i0 + b;
         if (ib < n && (badrow[a] || badrow[b])) {
             uint64_t &ab = lds[a * W + (ib >> 6)];  // holds entry (ia, ib)
@@ -123,6 +156,9 @@ __global__ __launch_bounds__(1024) void pack_check_kernel(const uint64_t *__rest
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
     if (tid == 0) bad = 0;
     __syncthreads();
+    const uint64_t lm = last_word_mask(n);
+    for (int i = tid; i < n; i += blockDim.x)
+        if (rows[(size_t)i * W + W - 1] & ~lm) bad = 1;
     for (int t = wave; t < W * W; t += nwaves) {  // wave-uniform
         const int I = t / W, J = t - I * W;
         if (J < I) continue;
@@ -604,10 +640,11 @@ hlf_status launch_workgroup_t(const uint64_t *rows, int n, int W, const FactorOu
 
 hlf_status launch_pack(const uint8_t *A, int n, int W, uint64_t *rows, int32_t *status,
                        hipStream_t stream) {
-    if (W >= 2 && (n & 15) == 0 && ((uintptr_t)A & 15u) == 0) {
+    if (W >= 2) {
+        const int vec16 = ((n & 15) == 0 && ((uintptr_t)A & 15u) == 0) ? 1 : 0;
         const unsigned blocks = (unsigned)((n + kPackRowsPerBlock - 1) / kPackRowsPerBlock);
         hipLaunchKernelGGL(pack_rows_kernel, dim3(blocks), dim3(kPackRowsThreads), 0, stream, A, n, W,
-                           rows);
+                           vec16, rows);
         if (hipGetLastError() != hipSuccess) return HLF_EDEVICE;
         hipLaunchKernelGGL(pack_check_kernel, dim3(1), dim3(1024), 0, stream, rows, n, W, status);
         return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;

@@ -106,7 +106,7 @@ def test_factor_large_workgroup(name, A):
     assert_record_matches(F, ref, name)
 
 
-@pytest.mark.parametrize("n", [5, 64, 100, 128, 256, 300, 320, 1008, 1024])
+@pytest.mark.parametrize("n", [5, 64, 65, 100, 128, 129, 256, 300, 320, 1001, 1008, 1023, 1024])
 def test_pack_matches_layout(n):
     print(f"[pack] n={n}", flush=True)
     A = random_symmetric(n, 77 + n, 0.4)
@@ -116,7 +116,7 @@ def test_pack_matches_layout(n):
     assert np.array_equal(hlf.as_uint64(rows), oracle_rows(A))
 
 
-@pytest.mark.parametrize("n", [4, 65, 128, 200, 256, 1008, 1024])
+@pytest.mark.parametrize("n", [4, 65, 100, 128, 129, 200, 256, 1001, 1008, 1024])
 def test_pack_rejects_asymmetric_and_non_binary(n):
     print(f"[pack-invalid] n={n}", flush=True)
     A = random_symmetric(n, 5, 0.5)
@@ -129,11 +129,12 @@ def test_pack_rejects_asymmetric_and_non_binary(n):
     assert int(st.item()) == hlf.HLF_ENOTSYM
 
 
-@pytest.mark.parametrize("n", [128, 1008])
+@pytest.mark.parametrize("n", [65, 128, 129, 1001, 1008, 1024])
 def test_pack_non_binary_rows_anywhere(n):
-    # n > 64 and a multiple of 16 packs rows across workgroups: a byte other
-    # than 0 and 1 in any row, alone or in adjacent rows, must give ENOTSYM,
-    # and a valid matrix right after must give OK again.
+    # n > 64 packs rows across workgroups (16-byte loads when n is a multiple
+    # of 16, byte loads otherwise): a byte other than 0 and 1 in any row,
+    # alone or in adjacent rows, must give ENOTSYM, and a valid matrix right
+    # after must give OK again.
     A = random_symmetric(n, 21, 0.5)
     for rows_bad in ([0], [n - 1], [5, 6], [n - 2, n - 1, 0]):
         B = A.copy()
