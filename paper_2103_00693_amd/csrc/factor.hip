@@ -1,7 +1,8 @@
 // Stage 1 of the two-stage scheme (the paper's CLA module, Section 2,
 // tasks (1)-(4)) on gfx950:
-//   * pack_dense_kernel: dense 0/1 matrix -> packed uint64 rows, with the
-//     symmetry / 0-1 validation of the problem statement (Section 1);
+//   * pack_dense_kernel (n <= 64), pack_rows_kernel + pack_check_kernel
+//     (n > 64): dense 0/1 matrix -> packed uint64 rows, with the symmetry /
+//     0-1 validation of the problem statement (Section 1);
 //   * factor_wave_kernel: one wavefront per instance (used for n <= 64; the
 //     batch path runs the same elimination for n <= 192); every lane keeps
 //     its rows in VGPRs, pivots are found with a ballot and the pivot row is
@@ -23,9 +24,10 @@ namespace hlf {
 namespace {
 
 // ---------------------------------------------------------------------------
-// A0: pack + validate.  One workgroup of 64*W threads packs A into bit rows in
-// LDS, then checks A = A^T: for column c, the ballot of bit c over the 64 rows
-// held by wave v is word v of column c, which must equal word v of row c.
+// A0: pack + validate for n <= 64 (larger n: the two launches above).  One
+// workgroup of 64*W threads packs A into bit rows in LDS, then checks A = A^T:
+// for column c, the ballot of bit c over the 64 rows held by wave v is word v
+// of column c, which must equal word v of row c.
 //
 // Packing: when n is a multiple of 16 and A is 16-byte aligned, each thread
 // loads 16 bytes (columns 16q..16q+15 of one row) per request, kPackU rows in
@@ -649,12 +651,7 @@ hlf_status launch_pack(const uint8_t *A, int n, int W, uint64_t *rows, int32_t *
         hipLaunchKernelGGL(pack_check_kernel, dim3(1), dim3(1024), 0, stream, rows, n, W, status);
         return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
     }
-    if (W <= 1) return launch_pack_t<1>(A, n, W, rows, status, stream);
-    if (W <= 2) return launch_pack_t<2>(A, n, W, rows, status, stream);
-    if (W <= 3) return launch_pack_t<3>(A, n, W, rows, status, stream);
-    if (W <= 4) return launch_pack_t<4>(A, n, W, rows, status, stream);
-    if (W <= 8) return launch_pack_t<8>(A, n, W, rows, status, stream);
-    return launch_pack_t<16>(A, n, W, rows, status, stream);
+    return launch_pack_t<1>(A, n, W, rows, status, stream);
 }
 
 hlf_status launch_factor(const uint64_t *rows, int n, int W, const FactorOut &out,
