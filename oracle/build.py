@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "libhlf_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+    cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
            "-o", LIB + ".tmp", SRC]
     if verbose:
         print(" ".join(cmd), flush=True)

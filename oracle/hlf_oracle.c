@@ -1,4 +1,5 @@
-/* Plain C oracle of the FS2D HLF stage-2 enumeration -- TEST INFRASTRUCTURE.
+/* Plain C oracle of the FS2D HLF stage-2 enumeration, sampling and membership
+ * -- TEST INFRASTRUCTURE.
  *
  * Only the tests, the smoke check and the benchmark's CPU-baseline leg load
  * this file's shared object.  It shares nothing with the HIP library.
@@ -19,8 +20,13 @@
  * of h(z) mod 2^64.  mix13 is the output function of Vigna's public-domain
  * SplitMix64 (Stafford's Mix13); GAMMA is SplitMix64's increment.
  *
+ * Samples use the same combination with a coefficient vector drawn from the
+ * project's counter-based SplitMix64 stream (or passed in); membership checks
+ * the problem's definition on the Ker(A) basis.
+ *
  * Parity pins: tests compare these functions with the Python oracle on small
- * ranges and with closed forms (per-qubit counts, full-rank identity hash).
+ * ranges and with closed forms (per-qubit counts, full-rank identity hash,
+ * samples satisfying every kernel equation, membership against brute force).
  */
 #include <stdint.h>
 #include <string.h>
@@ -50,16 +56,30 @@ int oracle_threads(void) {
 
 uint64_t oracle_mix13(uint64_t x) { return mix13(x); }
 
-/* z_i into z[0..W-1] by the direct definition. */
-static void solution_at(const uint64_t *basis, int r, int W, const uint64_t *shift,
-                        uint64_t i, uint64_t *z) {
-    uint64_t g = i ^ (i >> 1);
+/* l XOR (XOR over k < r with bit k of the coefficient vector c set of B_k)
+ * into z[0..W-1]; c is given as ceil(r/64) words.  Each term is B_k ANDed with
+ * an all-ones or all-zeros mask made from its coefficient bit (the same sum
+ * as "if bit k is set, add B_k", without a data-dependent branch). */
+static void combine(const uint64_t *basis, int r, int W, const uint64_t *shift,
+                    const uint64_t *c, uint64_t *z) {
+    if (W == 1) {  /* the same sum, written for one-word vectors */
+        uint64_t acc = shift[0];
+        for (int k = 0; k < r; ++k) acc ^= basis[k] & (0ULL - ((c[k >> 6] >> (k & 63)) & 1ULL));
+        z[0] = acc;
+        return;
+    }
     for (int w = 0; w < W; ++w) z[w] = shift[w];
     for (int k = 0; k < r; ++k) {
-        if ((g >> k) & 1ULL) {
-            for (int w = 0; w < W; ++w) z[w] ^= basis[(size_t)k * W + w];
-        }
+        const uint64_t m = 0ULL - ((c[k >> 6] >> (k & 63)) & 1ULL);
+        for (int w = 0; w < W; ++w) z[w] ^= basis[(size_t)k * W + w] & m;
     }
+}
+
+/* z_i into z[0..W-1] by the direct definition (coefficients g(i), r <= 62). */
+static void solution_at(const uint64_t *basis, int r, int W, const uint64_t *shift,
+                        uint64_t i, uint64_t *z) {
+    const uint64_t g = i ^ (i >> 1);
+    combine(basis, r, W, shift, &g, z);
 }
 
 static uint64_t hash_words(const uint64_t *z, int W) {
@@ -101,8 +121,9 @@ int oracle_enumerate_counter(const uint64_t *basis, int r, int W, const uint64_t
     return 0;
 }
 
-/* counts[j] = #solutions with bit j set (j < n); *hash = sum of h(z);
- * xorfold[w] = XOR of all solutions (may be NULL). */
+/* counts[j] = #solutions with bit j set (j < n; counts may be NULL when only
+ * the hash is wanted); *hash = sum of h(z); xorfold[w] = XOR of all solutions
+ * (may be NULL). */
 int oracle_reduce(const uint64_t *basis, int r, int W, int n, const uint64_t *shift,
                   uint64_t begin, uint64_t count, uint64_t *counts, uint64_t *hash,
                   uint64_t *xorfold) {
@@ -131,21 +152,72 @@ int oracle_reduce(const uint64_t *basis, int r, int W, int n, const uint64_t *sh
 #pragma omp for schedule(static)
         for (int64_t t = 0; t < cnt; ++t) {
             solution_at(basis, r, W, shift, begin + (uint64_t)t, z);
-            for (int j = 0; j < n; ++j) pc[j] += (z[j >> 6] >> (j & 63)) & 1ULL;
+            if (counts)
+                for (int j = 0; j < n; ++j) pc[j] += (z[j >> 6] >> (j & 63)) & 1ULL;
             ph += hash_words(z, W);
             for (int w = 0; w < W; ++w) px[w] ^= z[w];
         }
         part_hash[tid] = ph;
     }
-    for (int j = 0; j < n; ++j) counts[j] = 0;
+    if (counts) for (int j = 0; j < n; ++j) counts[j] = 0;
     *hash = 0;
     if (xorfold) for (int w = 0; w < W; ++w) xorfold[w] = 0;
     for (int t = 0; t < nt; ++t) {
-        for (int j = 0; j < n; ++j) counts[j] += part_counts[(size_t)t * n + j];
+        if (counts) for (int j = 0; j < n; ++j) counts[j] += part_counts[(size_t)t * n + j];
         *hash += part_hash[t];
         if (xorfold) for (int w = 0; w < W; ++w) xorfold[w] ^= part_xor[(size_t)t * W + w];
     }
     free(part_counts); free(part_hash); free(part_xor);
+    return 0;
+}
+
+/* Samples (uniform single solutions, App. A): for s in [0, num),
+ *   c_s = coeffs[s*R64 .. s*R64+R64-1] if coeffs is not NULL, else the
+ *         SplitMix64 outputs number s*R64 .. s*R64+R64-1 of the generator whose
+ *         state starts at seed (output k = mix13(seed + (k+1)*GAMMA), Steele,
+ *         Lea and Flood 2014), R64 = ceil(r/64), bits at positions >= r cleared;
+ *   out[s*W .. s*W+W-1] = l XOR (XOR over set bits k of c_s of B_k).
+ * Any r in [0, 64W]; OpenMP over the samples. */
+int oracle_sample(const uint64_t *basis, int r, int W, const uint64_t *shift, uint64_t seed,
+                  uint64_t num, const uint64_t *coeffs, uint64_t *out) {
+    if (W < 1 || W > 16 || r < 0 || r > 64 * W) return -1;
+    const int R64 = (r + 63) / 64;
+    int64_t cnt = (int64_t)num;
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < cnt; ++t) {
+        const uint64_t s = (uint64_t)t;
+        uint64_t c[16] = {0};
+        for (int w = 0; w < R64; ++w) {
+            const uint64_t k = s * (uint64_t)R64 + (uint64_t)w;
+            c[w] = coeffs ? coeffs[k] : mix13(seed + (k + 1ULL) * GAMMA);
+        }
+        if (r & 63) c[R64 - 1] &= (1ULL << (r & 63)) - 1ULL;
+        combine(basis, r, W, shift, c, out + (size_t)t * W);
+    }
+    return 0;
+}
+
+/* Membership by the problem's definition (Section 1) on a basis of Ker(A):
+ * member[s] = 1 iff q_f = 2 <z_s, k_f> (mod 4) for every kernel vector k_f,
+ * f < nk, with <z, k> the integer count of common ones and q_f = q(k_f) mod 4
+ * (the values of the quadratic form on the basis, passed in).  q is linear on
+ * Ker(A), so the basis vectors suffice.  OpenMP over the strings. */
+int oracle_membership(const uint64_t *kernel, int nk, const int *q, int W,
+                      const uint64_t *z, uint64_t num, uint8_t *member) {
+    if (W < 1 || W > 16 || nk < 0) return -1;
+    int64_t cnt = (int64_t)num;
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < cnt; ++t) {
+        const uint64_t *zs = z + (size_t)t * W;
+        int ok = 1;
+        for (int f = 0; f < nk; ++f) {
+            int64_t dot = 0;
+            for (int w = 0; w < W; ++w)
+                dot += __builtin_popcountll(zs[w] & kernel[(size_t)f * W + w]);
+            if ((((int64_t)q[f] - 2 * dot) % 4 + 4) % 4 != 0) ok = 0;
+        }
+        member[t] = (uint8_t)ok;
+    }
     return 0;
 }
 
