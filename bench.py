@@ -118,6 +118,52 @@ def copy_calibration():
     print(f"copied {src.numel() * 8} bytes x3", flush=True)
 
 
+
+class _Pipeline:
+    pass
+
+
+def headline_pipeline(hlf, torch, dev, stream, n_streams=HEADLINE_STREAMS):
+    """The headline step and its buffers.
+
+    Step k is ONE launch (hlf_batch_enumerate_overlap): it materialises all
+    2^r solutions of the 8 N=5 instances from record set k % 2S and, in extra
+    workgroups of the same launch, runs stage 1 (pack + validate + factor) of
+    the 8 instances into record set (k+S) % 2S for step k+S, S = n_streams.
+    Steps go to the S streams in turn, each with its own output set, so S
+    launches are in flight and each one's start-up and drain overlap the
+    others'; a launch depends only on the launch S steps back, on its own
+    stream.  Record sets 0..S-1 are factored here, before the first step.
+    """
+    from hlf_inputs import CONFIG2_SEEDS, grid_instance
+
+    P = _Pipeline()
+    n = 25
+    P.n_streams = n_streams
+    P.mats = [grid_instance(5, seed=s) for s in CONFIG2_SEEDS]
+    P.Bs = [hlf.Batch([n] * len(P.mats)) for _ in range(2 * n_streams)]
+    P.A = P.Bs[0].dense_input(P.mats, device=dev)
+    P.streams = [stream] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
+    for Bk in P.Bs[:n_streams]:
+        Bk.factor_dense(P.A, stream=stream)
+    stream.synchronize()
+    if not all(st == hlf.HLF_OK for Bk in P.Bs[:n_streams] for st in Bk.statuses()):
+        raise RuntimeError("factor failed")
+    P.ranks = [int(r) for r in P.Bs[0].ranks()]
+    P.counts = [1 << r for r in P.ranks]
+    P.out_sets = [[torch.empty(c, dtype=torch.int32, device=dev) for c in P.counts] for _ in P.streams]
+    inst = list(range(len(P.mats)))
+    zeros = [0] * len(P.mats)
+
+    def step(k):
+        P.Bs[k % (2 * n_streams)].enumerate_overlap(inst, zeros, P.counts, P.out_sets[k % n_streams], 32,
+                                                    P.Bs[(k + n_streams) % (2 * n_streams)], P.A,
+                                                    stream=P.streams[k % n_streams])
+
+    P.step = step
+    return P
+
+
 def tiny_mode(hlf, torch, stream, dev):
     """N=4 grid (n = 16), all edges, seed 0: pack + factor + materialise all
     2^r solutions as uint16 -- a latency measurement (a single launch chain)."""
@@ -278,7 +324,8 @@ def verify_mode(hlf, torch, stream, dev):
     z = hlf.sample(F, 11, num, stream=stream)
     mem = torch.empty(num, dtype=torch.uint8, device=dev)
     t_mem = _timed(torch, stream, lambda: hlf.membership(F, z, out=mem, stream=stream), 5)
-    xeb_exact = hlf.linear_xeb(n, r, mem)
+    # linear XEB estimate 2^(n-r) * (fraction of members) - 1 (report arithmetic only)
+    xeb_exact = (2.0 ** (n - r)) * (int(mem.sum().item()) / num) - 1.0
     g = torch.Generator(device=dev)
     g.manual_seed(5)
     u = torch.randint(-(1 << 62), 1 << 62, (num, 16), dtype=torch.int64, device=dev, generator=g)
@@ -432,41 +479,14 @@ def main():
     dev = torch.device("cuda", 0)
 
     # ---------------- headline workload: N=5 grid, 8 seeds ----------------
-    # Step k is ONE launch (hlf_batch_enumerate_overlap): it materialises all
-    # 2^r solutions of the 8 instances from record set k % 2S and, in extra
-    # workgroups of the same launch, runs stage 1 (pack + validate + factor)
-    # of the 8 instances into record set (k+S) % 2S for step k+S, S =
-    # HEADLINE_STREAMS.  Steps go to the S streams in turn, each with its own
-    # output set, so S launches are in flight and each one's start-up and
-    # drain overlap the others'; a launch depends only on the launch S steps
-    # back, on its own stream.  Stage 1 of the first S timed steps ran in the
-    # last warm-up launches; the last S timed launches run stage 1 for steps
-    # past the timed ones, so the timed region holds exactly `steps` stage-1
-    # and `steps` stage-2 passes.
-    n = 25
-    mats = [grid_instance(5, seed=s) for s in CONFIG2_SEEDS]
-    n_streams = HEADLINE_STREAMS
-    Bs = [hlf.Batch([n] * len(mats)) for _ in range(2 * n_streams)]
-    A = Bs[0].dense_input(mats, device=dev)
-    streams = [stream] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
-    for Bk in Bs[:n_streams]:
-        Bk.factor_dense(A, stream=stream)
-    stream.synchronize()
-    if not all(st == hlf.HLF_OK for Bk in Bs[:n_streams] for st in Bk.statuses()):
-        raise RuntimeError("factor failed")
-    ranks = [int(r) for r in Bs[0].ranks()]
-    counts = [1 << r for r in ranks]
-    out_sets = [[torch.empty(c, dtype=torch.int32, device=dev) for c in counts] for _ in streams]
+    P = headline_pipeline(hlf, torch, dev, stream)
+    mats, Bs, A, streams, out_sets, step = P.mats, P.Bs, P.A, P.streams, P.out_sets, P.step
+    n_streams, ranks, counts = P.n_streams, P.ranks, P.counts
     outs = out_sets[0]
     inst = list(range(len(mats)))
     zeros = [0] * len(mats)
     solutions_per_step = sum(counts)
     bytes_per_step = 4 * solutions_per_step
-
-    def step(k):
-        Bs[k % (2 * n_streams)].enumerate_overlap(inst, zeros, counts, out_sets[k % n_streams], 32,
-                                                  Bs[(k + n_streams) % (2 * n_streams)], A,
-                                                  stream=streams[k % n_streams])
 
     warmup = max(n_streams, args.warmup)
     for k in range(warmup):

@@ -80,7 +80,7 @@ typedef enum hlf_status {
     HLF_ERANGE = -3,      /* index range outside [0, 2^r), or r > 62            */
     HLF_ENOMEM = -4,      /* a capacity limit was exceeded                       */
     HLF_EDEVICE = -5,     /* a HIP call failed                                   */
-    HLF_ECANCELLED = -6,  /* work was cancelled by the host                      */
+    /* -6 is not used: no call can be cancelled once enqueued                    */
     HLF_EINTERNAL = -7    /* an internal invariant failed (q odd on Ker(A))      */
 } hlf_status;
 
@@ -364,14 +364,18 @@ hlf_status hlf_batch_solve(hlf_batch b, const uint8_t *A_dev, int32_t num, const
  * 2^r solutions as chunks on a device queue, which all wavefronts drain.
  * Results: counts[piv_off[i] + j], hash[i] over all 2^r_i solutions (zero
  * for instances with r_i > max_rank).  Needs max_n <= 192 (else HLF_EINVAL).
- * params NULL selects defaults (or the tuned values, if hlf_batch_tune ran). */
+ * params NULL selects defaults (or the tuned values, if hlf_batch_tune ran).
+ * The queue counts chunks in 40 bits: HLF_EINVAL unless
+ * count * 2^max(0, max_rank - chunk_log2) < 2^40 (count = instances).         */
 hlf_status hlf_batch_reduce(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,
                             const hlf_batch_params *params, hipStream_t stream);
 
 /* Autotuner: times hlf_batch_reduce on this batch over a grid of
  * (chunk_log2, waves_per_cu) candidates on `stream` (synchronising it) and
  * stores the fastest as the batch default; *best and *best_ms receive it.
- * Every candidate produces the same results.                                  */
+ * Every candidate produces the same results.  Candidates whose chunk count
+ * would not fit the queue (see hlf_batch_reduce) are skipped; HLF_EINVAL if
+ * none fits.                                                                  */
 hlf_status hlf_batch_tune(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,
                           hlf_batch_params *best, float *best_ms, hipStream_t stream);
 

@@ -491,6 +491,17 @@ bool params_ok(const hlf_batch_params &p) {
     return p.chunk_log2 >= 10 && p.chunk_log2 <= 30 && p.waves_per_cu >= 1 && p.waves_per_cu <= 16;
 }
 
+// The claim word keeps the running chunk total in its low kClaimShift bits:
+// every instance with r <= max_rank claims max(1, 2^(r - chunk_log2)) chunks,
+// so the total over the batch must stay below 2^kClaimShift (else it would
+// carry into the slot field).
+bool claims_fit(const hlf_batch_s *b, int max_rank, int chunk_log2) {
+    const int e = max_rank > chunk_log2 ? max_rank - chunk_log2 : 0;
+    if (e >= hlf::kClaimShift) return false;
+    const unsigned long long per = 1ull << e;
+    return (unsigned long long)b->count < ((1ull << hlf::kClaimShift) / per);
+}
+
 template <int WMAX>
 hlf_status launch_batch_reduce_t(hlf_batch_s *b, const uint8_t *A, int max_rank,
                                  const hlf_batch_params &p, hipStream_t stream) {
@@ -842,7 +853,7 @@ hlf_status hlf_batch_reduce(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,
     if (!b || !A_dev || max_rank < 0 || max_rank > HLF_MAX_ENUM_RANK) return HLF_EINVAL;
     if (b->max_n > 192) return HLF_EINVAL;
     const hlf_batch_params p = params ? *params : b->tuned;
-    if (!params_ok(p)) return HLF_EINVAL;
+    if (!params_ok(p) || !claims_fit(b, max_rank, p.chunk_log2)) return HLF_EINVAL;
     return batch_reduce_impl(b, A_dev, max_rank, p, stream);
 }
 
@@ -873,7 +884,10 @@ hlf_status hlf_batch_tune(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,
     hlf_batch_params bestp = b->tuned;
     float bestt = 1e30f;
     hlf_status st = HLF_OK;
+    bool any = false;
     for (int c : chunks) {
+        if (!claims_fit(b, max_rank, c)) continue;
+        any = true;
         for (int w : waves) {
             const hlf_batch_params p = {c, w};
             st = batch_reduce_impl(b, A_dev, max_rank, p, stream);  // warm
@@ -899,6 +913,7 @@ hlf_status hlf_batch_tune(hlf_batch b, const uint8_t *A_dev, int32_t max_rank,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != HLF_OK) return st;
+    if (!any) return HLF_EINVAL;
     b->tuned = bestp;
     b->has_tuned = true;
     {
@@ -915,7 +930,7 @@ hlf_status hlf_batch_graph_capture(hlf_batch b, const uint8_t *A_dev, int32_t ma
     if (!b || !A_dev || max_rank < 0 || max_rank > HLF_MAX_ENUM_RANK) return HLF_EINVAL;
     if (b->max_n > 192) return HLF_EINVAL;
     const hlf_batch_params p = params ? *params : b->tuned;
-    if (!params_ok(p)) return HLF_EINVAL;
+    if (!params_ok(p) || !claims_fit(b, max_rank, p.chunk_log2)) return HLF_EINVAL;
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return HLF_EDEVICE;
     hlf_status st = HLF_OK;

@@ -62,7 +62,6 @@ const char *hlf_status_string(int32_t status) {
         case HLF_ERANGE: return "HLF_ERANGE: index range outside [0, 2^r) or r > 62";
         case HLF_ENOMEM: return "HLF_ENOMEM: capacity exceeded";
         case HLF_EDEVICE: return "HLF_EDEVICE: HIP launch failed";
-        case HLF_ECANCELLED: return "HLF_ECANCELLED: cancelled";
         case HLF_EINTERNAL: return "HLF_EINTERNAL: internal invariant failed";
         default: return "unknown hlf_status";
     }

@@ -24,7 +24,6 @@ HLF_ENOTSYM = -2
 HLF_ERANGE = -3
 HLF_ENOMEM = -4
 HLF_EDEVICE = -5
-HLF_ECANCELLED = -6
 HLF_EINTERNAL = -7
 HLF_MAX_N = 1024
 HLF_MAX_ENUM_RANK = 62
@@ -346,15 +345,6 @@ def membership(F: Factors, z: torch.Tensor, out: torch.Tensor | None = None,
     _check(lib().hlf_membership(F.c, _ptr(z) if num else None, num, _ptr(out) if num else None,
                                 _stream(stream)), "hlf_membership")
     return out
-
-
-def linear_xeb(n: int, r: int, member: torch.Tensor) -> float:
-    """Linear cross-entropy estimate 2^(n-r) * mean(member) - 1 from membership
-    flags (ideal probability 2^-r on the solution set, 0 elsewhere)."""
-    num = int(member.numel())
-    if num == 0:
-        raise HlfError(HLF_EINVAL, "no samples")
-    return (2.0 ** (n - r)) * (int(member.sum().item()) / num) - 1.0
 
 
 # ---------------------------------------------------------------------------

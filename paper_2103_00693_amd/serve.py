@@ -236,8 +236,9 @@ class Server:
                     self.cache_bytes -= e.nbytes
         # The pinned buffer itself is handed over (numpy keeps it alive).
         data = a.host_out.numpy() if a.host_out is not None else None
+        arrival = a.req.arrival if self._realtime else 0.0
         return Result(rid=a.req.rid, status=a.status, n=a.n, rank=a.rank, kind=a.kind, data=data,
-                      admitted=a.admitted, finished=now, latency=now - a.req.arrival,
+                      admitted=a.admitted, finished=now, latency=now - arrival,
                       cache_hit=a.cache_hit)
 
     # -- the loop ---------------------------------------------------------------
@@ -249,6 +250,7 @@ class Server:
         for q in pending:
             if self.footprint(q.A.shape[0]) > self.budget:
                 raise hlf.HlfError(hlf.HLF_ENOMEM, f"request {q.rid} exceeds the HBM budget")
+        self._realtime = realtime  # without it every request counts as arrived at t = 0
         active: dict[int, _Active] = {}
         free = list(range(self.slots))
         done: list[Result] = []
@@ -264,8 +266,6 @@ class Server:
                     if not self._fits(fp):
                         break
                 req = pending.popleft()
-                if not realtime:
-                    req.arrival = 0.0
                 slot = free.pop()
                 active[slot] = self._admit(req, slot, now)
                 progressed = True

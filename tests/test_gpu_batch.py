@@ -154,6 +154,23 @@ def test_batch_reduce_all_launch_shapes_agree():
     B.close()
 
 
+def test_batch_reduce_rejects_chunk_totals_beyond_the_queue_word():
+    # the queue counts chunks in 40 bits: count * 2^(max_rank - chunk_log2) must stay below 2^40
+    mats = mixed_batch(seed=5, count=300, Ns=range(3, 6))
+    B = hlf.Batch([m.shape[0] for m in mats])
+    A = B.dense_input(mats)
+    for max_rank, chunk in ((62, 10), (50, 10), (62, 30)):
+        with pytest.raises(hlf.HlfError):
+            B.reduce(A, max_rank, hlf.BatchParams(chunk, 4))
+        with pytest.raises(hlf.HlfError):
+            B.graph_capture(A, max_rank, hlf.BatchParams(chunk, 4))
+    print("[batch] claim limit: accepted shape", flush=True)
+    B.reduce(A, 20, hlf.BatchParams(10, 4))  # 300 * 2^10 chunks fit
+    torch.cuda.synchronize()
+    assert all(s == hlf.HLF_OK for s in B.statuses())
+    B.close()
+
+
 def test_batch_reduce_w1_only_batch():
     mats = [grid_instance(N, p=p, seed=s) for N, p, s in
             [(3, 1.0, 0), (4, 0.5, 1), (5, 1.0, 2), (6, 0.3, 3), (2, 1.0, 4), (1, 1.0, 5)]]

@@ -218,7 +218,7 @@ def test_membership_n1024_samples_flips_and_xeb():
     m = hlf.membership(F, z)
     torch.cuda.synchronize()
     assert int(m.sum().item()) == 20000
-    assert hlf.linear_xeb(n, r, m) == 2.0 ** (n - r) - 1.0
+    assert O.linear_xeb(n, r, m.cpu().numpy().tolist()) == 2.0 ** (n - r) - 1.0
     # flip one free coordinate f of every sample: <k_f, z> changes, so no sample stays a solution
     piv = set(int(p) for p in F.pivots.cpu().numpy()[:r])
     free = [c for c in range(n) if c not in piv]
