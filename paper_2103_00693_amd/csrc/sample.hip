@@ -69,13 +69,12 @@ __global__ __launch_bounds__(SampleShape<WMAX>::kThreads) void sample_kernel(
 // Large n: sampling as a dense product over GF(2) on the matrix cores.
 // Z = C * Bm mod 2, C the num x r coefficient bits, Bm the r x n basis bits,
 // on v_mfma_scale_f32_32x32x64_f8f6f4 with 4-bit E2M1 operands (scale 1):
-// fp32 sums of products that are 0 or exactly 1, so a sum is the integer
-// count of common set bits (<= r <= 1024, exact) and its bit 0 is the GF(2)
-// product.  A workgroup owns one group of 128 output bits (4 column chunks of
-// 32); its B operands, in the register layout of the instruction, are built
-// once in LDS (ceil(r/64) x 4 chunks of 64 lanes x 16 bytes).  Each wave
-// multiplies blocks of 32 samples by them, the A operand coming straight from
-// the coefficient words.
+// fp32 sums of products that are 0 or exactly 1.  A workgroup owns one group
+// of 32*JC output bits (JC column chunks of 32); its B operands, in the
+// register layout of the instruction, are built once in LDS (ceil(r/64) x JC
+// chunks of 64 lanes x 16 bytes).  Each wave multiplies blocks of 32 samples
+// by them, the A operand coming straight from the coefficient words, which
+// a wave generates once per block for all JC chunks.
 //
 // K chunk kc is coefficient word kc: lane l covers sample row l % 32 and the
 // 32-bit half h = l / 32 of the word, y.  Nibble t of operand dword d stands
@@ -93,62 +92,60 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-constexpr int kMfmaJC = 4;       // 32-bit column chunks per workgroup
-constexpr int kMfmaWaves = 16;   // four per SIMD, 32 samples each at a time
 constexpr int kMfmaMaxKC = HLF_MAX_N / 64;
 constexpr int kE2M1 = 4;         // operand format code of the instruction
 constexpr int kScaleOne = 127;   // E8M0 scale 2^0
 
-__global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
+// JC column chunks (JC/2 words of every sample) per workgroup, WAVES waves.
+template <int JC, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
     FactorIn f, uint64_t seed, uint64_t num, const uint64_t *__restrict__ coeffs,
     uint64_t *__restrict__ out) {
-    __shared__ __align__(16) uint32_t Bop[kMfmaMaxKC * kMfmaJC * 64 * 4];  // 64 KiB
-    __shared__ uint64_t BT[128 * 16];                                    // 16 KiB
+    constexpr int QW = JC / 2;  // words per workgroup
+    __shared__ __align__(16) uint32_t Bop[kMfmaMaxKC * JC * 64 * 4];
     if (*(volatile int32_t *)f.status != HLF_OK) return;
     const int r = *f.rank;
     const int W = f.words;
-    const int cg = blockIdx.x;        // words 2cg, 2cg+1 of every sample
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, m = lane & 31;
     const int KC = (r + 63) >> 6;     // K chunks of 64 = coefficient words
-    const int w0 = 2 * cg;
-    const bool has1 = w0 + 1 < W;
-    // Transpose: BT[j * 16 + kc] bit t = bit j (of this group's 128 columns)
-    // of B_{64kc+t}.  A wave takes one (kc, word) tile: lane t holds the word
-    // of row 64kc+t, and after the transpose lane b holds column b.
-    for (int t = wave; t < 2 * KC; t += kMfmaWaves) {
-        const int kc = t >> 1, q = t & 1;
+    const int w0 = QW * (int)blockIdx.x;
+    const int nq = min(QW, W - w0);   // words of this group that exist
+    // B operands.  A wave takes one (kc, word q) tile: lane t loads the word
+    // of B_{64kc+t}; after the 64x64 transpose lane b holds bit 64q + b of
+    // every row of the tile (bit t <-> k = 64kc + t).  One permlane32 swap of
+    // the halves then gives lane (h, m) half h of column 64q + m (chunk 2q,
+    // first) and of column 64q + 32 + m (chunk 2q + 1, second).  Nibble t of
+    // dword d holds k = 32h + 4t + d at position 2, 1, 0, 0 for d = 0..3.
+    for (int t = wave; t < KC * QW; t += WAVES) {
+        const int kc = t / QW, q = t - kc * QW;
         const int k = 64 * kc + lane;
-        const uint64_t x = (k < r && (q == 0 || has1)) ? f.basis[(size_t)k * W + w0 + q] : 0ull;
-        BT[(64 * q + lane) * 16 + kc] = wave_transpose64(x);
-    }
-    __syncthreads();
-    // B operand of chunk (kc, jc): lane (h, n), dword d, nibble t holds bit
-    // j = 32jc + n of B_k, k = 64kc + 32h + 4t + d, at nibble position 2, 1,
-    // 0, 0 for d = 0, 1, 2, 3.
-    for (int t = wave; t < KC * kMfmaJC; t += kMfmaWaves) {
-        const int kc = t / kMfmaJC, jc = t - kc * kMfmaJC;
-        const int j = 32 * jc + m;
-        const uint32_t y = (uint32_t)(BT[j * 16 + kc] >> (32 * h));
-        uint32_t *dst = &Bop[((size_t)t * 64 + lane) * 4];
-        dst[0] = (y & 0x11111111u) << 2;
-        dst[1] = y & 0x22222222u;
-        dst[2] = (y & 0x44444444u) >> 2;
-        dst[3] = (y & 0x88888888u) >> 3;
+        const uint64_t x = (k < r && q < nq) ? f.basis[(size_t)k * W + w0 + q] : 0ull;
+        const uint64_t xt = wave_transpose64(x);
+        const auto y2 = __builtin_amdgcn_permlane32_swap((uint32_t)xt, (uint32_t)(xt >> 32), false, false);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const uint32_t y = y2[e];
+            const v4i d = {(int)((y & 0x11111111u) << 2), (int)(y & 0x22222222u),
+                           (int)((y & 0x44444444u) >> 2), (int)((y & 0x88888888u) >> 3)};
+            *reinterpret_cast<v4i *>(&Bop[((size_t)(kc * JC + 2 * q + e) * 64 + lane) * 4]) = d;
+        }
     }
     __syncthreads();
 
-    const uint64_t l0 = f.shift[w0], l1 = has1 ? f.shift[w0 + 1] : 0ull;
+    uint64_t l[QW];
+#pragma unroll
+    for (int q = 0; q < QW; ++q) l[q] = q < nq ? f.shift[w0 + q] : 0ull;
     const uint64_t lastmask = (r & 63) ? ((1ull << (r & 63)) - 1ull) : ~0ull;
     // This workgroup's samples: a contiguous run of 32-sample blocks, taken by
     // its waves in turn (every SIMD of the CU gets the same number of blocks).
     const uint64_t nblk = (num + 31) >> 5;
     const uint64_t per_wg = (nblk + gridDim.y - 1) / gridDim.y;
     const uint64_t blk_end = min(nblk, (uint64_t)(blockIdx.y + 1) * per_wg);
-    for (uint64_t blk = (uint64_t)blockIdx.y * per_wg + wave; blk < blk_end; blk += kMfmaWaves) {
+    for (uint64_t blk = (uint64_t)blockIdx.y * per_wg + wave; blk < blk_end; blk += WAVES) {
         const uint64_t s = 32ull * blk + (uint64_t)m;  // this lane's A row
         const bool live = s < num;
-        v16f acc[kMfmaJC];
+        v16f acc[JC];
         // Coefficient words 2p, 2p+1 of this row are K chunks 2p, 2p+1: lane
         // half h generates word 2p+h (SplitMix64 state seed + (ctr+1) gamma,
         // advanced by 2 gamma per step).  One swap of the upper 32 lanes of
@@ -165,23 +162,21 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
             state += 2 * kGamma;
             return __builtin_amdgcn_permlane32_swap((uint32_t)mine, (uint32_t)(mine >> 32), false, false);
         };
-        // The products of K chunk kc; the first chunk starts from a zero
-        // accumulator (an inline constant of the instruction).
+        // The products of K chunk kc (the operands of words beyond W are zero).
         auto chunk = [&](int kc, uint32_t y, bool first) {
             const v8i a = {(int)(y & 0x11111111u), (int)(y & 0x22222222u),
                            (int)(y & 0x44444444u), (int)((y >> 1) & 0x44444444u), 0, 0, 0, 0};
 #pragma unroll
-            for (int jc = 0; jc < kMfmaJC; ++jc) {
-                const v4i b4 = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * kMfmaJC + jc) * 64 + lane) * 4]);
+            for (int jc = 0; jc < JC; ++jc) {
+                const v4i b4 = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * JC + jc) * 64 + lane) * 4]);
                 const v8i b = {b4[0], b4[1], b4[2], b4[3], 0, 0, 0, 0};
                 acc[jc] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
                     b, a, first ? v16f{} : acc[jc], kE2M1, kE2M1, 0, kScaleOne, 0, kScaleOne);
             }
         };
-        // The other waves of the SIMD cover the operand reads' latency.
         if (KC == 0) {
 #pragma unroll
-            for (int jc = 0; jc < kMfmaJC; ++jc) acc[jc] = v16f{};
+            for (int jc = 0; jc < JC; ++jc) acc[jc] = v16f{};
         } else {
             auto ys = words(0);
             chunk(0, ys[0], true);
@@ -195,9 +190,9 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
         // Register i holds the count of bit 8(i/4) + 4h + i%4: the low bytes of
         // registers u, 4+u, 8+u, 12+u go to bytes 0..3 of one dword, whose
         // bits 0 then move to bits 8t + u.
-        uint32_t word[kMfmaJC];
+        uint32_t word[JC];
 #pragma unroll
-        for (int jc = 0; jc < kMfmaJC; ++jc) {
+        for (int jc = 0; jc < JC; ++jc) {
             uint32_t c[16];
 #pragma unroll
             for (int i = 0; i < 16; ++i) c[i] = (uint32_t)acc[jc][i];
@@ -214,28 +209,38 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void sample_mfma_kernel(
         }
         const uint64_t so = 32ull * blk + (uint64_t)lane;  // row `lane` for lanes < 32
         if (lane < 32 && so < num) {
-            out[so * W + w0] = (((uint64_t)word[1] << 32) | word[0]) ^ l0;
-            if (has1) out[so * W + w0 + 1] = (((uint64_t)word[3] << 32) | word[2]) ^ l1;
+#pragma unroll
+            for (int q = 0; q < QW; ++q)
+                if (q < nq)
+                    out[so * W + w0 + q] = (((uint64_t)word[2 * q + 1] << 32) | word[2 * q]) ^ l[q];
         }
     }
 }
 
-hlf_status launch_sample_mfma(const FactorIn &f, uint64_t seed, uint64_t num,
-                              const uint64_t *coeffs, uint64_t *out, hipStream_t stream) {
+template <int JC, int WAVES>
+hlf_status launch_sample_mfma_t(const FactorIn &f, uint64_t seed, uint64_t num,
+                                const uint64_t *coeffs, uint64_t *out, hipStream_t stream) {
     const int W = f.words;
-    const unsigned groups = (unsigned)((W + 1) / 2);
+    const unsigned groups = (unsigned)((W + JC / 2 - 1) / (JC / 2));
     const uint64_t blocks32 = (num + 31) / 32;
-    // One workgroup per CU (16 waves of about 100 VGPRs; 80 KiB of LDS for
-    // the B operands and their transpose); every workgroup builds the
-    // operands once and takes a contiguous run of 32-sample blocks, at least
-    // one per wave.
+    // One workgroup per CU; every workgroup builds the operands once and
+    // takes a contiguous run of 32-sample blocks, at least one per wave.
     uint64_t y = (uint64_t)device_cu_count() / groups;
-    const uint64_t most = (blocks32 + kMfmaWaves - 1) / kMfmaWaves;
+    const uint64_t most = (blocks32 + WAVES - 1) / WAVES;
     if (y > most) y = most;
     if (y == 0) y = 1;
-    hipLaunchKernelGGL(sample_mfma_kernel, dim3(groups, (unsigned)y),
-                       dim3(64 * kMfmaWaves), 0, stream, f, seed, num, coeffs, out);
+    hipLaunchKernelGGL((sample_mfma_kernel<JC, WAVES>), dim3(groups, (unsigned)y),
+                       dim3(64 * WAVES), 0, stream, f, seed, num, coeffs, out);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
+}
+
+hlf_status launch_sample_mfma(const FactorIn &f, uint64_t seed, uint64_t num,
+                              const uint64_t *coeffs, uint64_t *out, hipStream_t stream) {
+    // Four words (256 output bits) per workgroup from W = 4: the coefficient
+    // words and A operands of a block then serve 8 products per K chunk, and
+    // 12 waves (three per SIMD, 164 VGPRs each) share the 128 KiB of operands.
+    if (f.words >= 4) return launch_sample_mfma_t<8, 12>(f, seed, num, coeffs, out, stream);
+    return launch_sample_mfma_t<4, 16>(f, seed, num, coeffs, out, stream);
 }
 
 template <int WMAX>
