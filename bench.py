@@ -374,38 +374,61 @@ def batch_mode(hlf, torch, stream, dev):
     counts_b, hashes_b = B.reduce_results()
     sols = sum(1 << r for r in ranks if r <= max_rank)
 
-    # plain per-instance launches, same outputs
-    t0 = time.perf_counter()
-    Fs = []
+    # Plain per-instance launches, same outputs.  Inputs are uploaded and the
+    # records allocated before timing; the timed parts are the per-instance
+    # pack + factor launches and the per-instance reduce launches (HIP events
+    # on the stream, as for the batched run); between them one copy brings
+    # every rank to the host (host time, reported separately).
+    Ads = [torch.from_numpy(m).to(dev) for m in mats]
+    rows_l = [torch.empty((m.shape[0], hlf.words_for(m.shape[0])), dtype=torch.int64, device=dev)
+              for m in mats]
+    pst = torch.empty(1, dtype=torch.int32, device=dev)
+    Fs = [hlf.Factors(m.shape[0], device=dev, kernel=False) for m in mats]
+    outs = {}
+    for i, m in enumerate(mats):
+        n = m.shape[0]
+        outs[i] = (torch.empty(n, dtype=torch.int64, device=dev), torch.empty(1, dtype=torch.int64, device=dev))
+    e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
     with torch.cuda.stream(stream):
-        for m in mats:
-            n = m.shape[0]
-            Ad = torch.from_numpy(m).to(dev, non_blocking=False)
-            rows, _ = hlf.pack_dense(Ad, stream=stream)
-            Fs.append(hlf.factor(rows, n, hlf.Factors(n, device=dev, kernel=False), stream=stream))
+        rank_view = torch.empty(len(mats), dtype=torch.int32, device=dev)
         stream.synchronize()
-        rp = [int(F.rank.item()) for F in Fs]
-        outs = {}
+        e0.record(stream)
+        for i, m in enumerate(mats):
+            hlf.pack_dense(Ads[i], rows_l[i], pst, stream=stream)
+            hlf.factor(rows_l[i], m.shape[0], Fs[i], stream=stream)
+        e1.record(stream)
+        t0 = time.perf_counter()
+        torch.stack([F.rank.view(()) for F in Fs], out=rank_view)
+        rp = [int(r) for r in rank_view.cpu().numpy()]
+        t_ranks = time.perf_counter() - t0
+        e2.record(stream)
         for i, F in enumerate(Fs):
             if rp[i] <= max_rank:
-                outs[i] = hlf.enumerate_reduce(F, 0, 1 << rp[i], want_xorfold=False, stream=stream)
+                c, h = outs[i]
+                hlf.enumerate_reduce(F, 0, 1 << rp[i], counts=c, hash_out=h, want_xorfold=False,
+                                     stream=stream)
+        e3.record(stream)
         stream.synchronize()
-    plain_s = time.perf_counter() - t0
+    plain_s = (e0.elapsed_time(e1) + e2.elapsed_time(e3)) * 1e-3
+    reduced = [i for i in range(len(mats)) if rp[i] <= max_rank]
     same = rp == ranks and all(
-        int(hlf.as_uint64(h)[0]) == hashes_b[i] and
-        (hlf.as_uint64(c) == counts_b[i]).all() for i, (c, h, _) in outs.items())
+        int(hlf.as_uint64(outs[i][1])[0]) == hashes_b[i] and
+        (hlf.as_uint64(outs[i][0]) == counts_b[i]).all() for i in reduced)
     B.close()
     return {
         "workload": "4096 grid instances, N ~ U{3..12}, p ~ U{0.3,0.5,1.0}, diagonal Bernoulli(0.5): "
                     "factor all, reduce (counts + hash) every instance with r <= 28",
-        "reduced_instances": len(outs),
+        "reduced_instances": len(reduced),
         "solutions": sols,
         "batched": {"instances_per_s": round(4096 / batched_s, 1), "ms": round(batched_s * 1e3, 3),
                     "solutions_per_s_G": round(sols / batched_s / 1e9, 2),
                     "params": {"chunk_log2": params.chunk_log2, "waves_per_cu": params.waves_per_cu},
                     "launch": "hipGraph replay of queue reset + one persistent kernel"},
         "plain": {"instances_per_s": round(4096 / plain_s, 1), "ms": round(plain_s * 1e3, 3),
-                  "launch": "pack + factor per instance, then reduce per small-rank instance (host timed)"},
+                  "rank_readback_ms": round(t_ranks * 1e3, 3),
+                  "launch": "pack + factor per instance, then reduce per small-rank instance; inputs resident "
+                            "and records preallocated; HIP events around the launches (the rank readback "
+                            "between them is not included)"},
         "speedup": round(plain_s / batched_s, 2),
         "identical_outputs": bool(same),
     }
@@ -449,6 +472,60 @@ def serve_mode(torch):
                              "p99_ms": round(percentile(lat, 99), 3),
                              "max_in_flight_bytes": srv.max_in_flight})
     return out
+
+
+def mode_cpu_baselines(modes, seconds):
+    """The oracle (plain C per-index definitions, Python stage 1) on this
+    host's cores for the secondary workloads, each on a bounded sample."""
+    import numpy as np
+
+    from hlf_inputs import CONFIG3_SEEDS, batch_instances, grid_instance
+    from oracle import c_oracle, hlf_oracle
+
+    cores = c_oracle.threads()
+    if "reduce" in modes:
+        # the 16 random 2^20-index chunks per N=6 seed that the parity tests check
+        done, t_all = 0, 0.0
+        for s in CONFIG3_SEEDS:
+            Fo = hlf_oracle.factor(grid_instance(6, p=0.5, seed=s))
+            rng = np.random.default_rng(1000 + s)
+            for _ in range(16):
+                b = int(rng.integers(0, (1 << Fo["rank"]) - (1 << 20)))
+                t0 = time.perf_counter()
+                c_oracle.reduce_range(Fo, b, 1 << 20)
+                t_all += time.perf_counter() - t0
+                done += 1 << 20
+        modes["reduce"]["cpu_baseline"] = {
+            "value": round(done / t_all / 1e9, 4), "unit": "G solutions/s", "cores": cores, "kind": "oracle",
+            "sample": f"16 chunks of 2^20 solutions per N=6 seed (64 chunks, {done} solutions) through the "
+                      f"plain C per-index oracle (counts + hash + xorfold), {t_all:.2f} s"}
+    if "sample" in modes:
+        Fo = hlf_oracle.factor(grid_instance(32, p=0.5, seed=17))
+        t0 = time.perf_counter()
+        num = 0
+        while time.perf_counter() - t0 < min(seconds, 3.0) or num == 0:
+            c_oracle.sample(Fo, num, 65536)
+            num += 65536
+        t = time.perf_counter() - t0
+        modes["sample"]["cpu_baseline"] = {
+            "value": round(num / t, 1), "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"{num} samples at n=1024 (r={Fo['rank']}) through the plain C per-sample oracle, {t:.2f} s"}
+    if "batch" in modes:
+        insts = batch_instances(4096, master_seed=0)
+        t0 = time.perf_counter()
+        k, sols = 0, 0
+        while k < len(insts) and (time.perf_counter() - t0 < seconds or k == 0):
+            Fo = hlf_oracle.factor(insts[k][3])
+            if Fo["rank"] <= 28:
+                c_oracle.reduce_range(Fo, 0, 1 << Fo["rank"])
+                sols += 1 << Fo["rank"]
+            k += 1
+        t = time.perf_counter() - t0
+        modes["batch"]["cpu_baseline"] = {
+            "value": round(k / t, 2), "unit": "instances/s", "cores": cores, "kind": "oracle",
+            "sample": f"the first {k} of the 4096 instances (stage 1 in the Python oracle, one thread; "
+                      f"counts + hash of every solution of the r <= 28 ones, {sols} solutions, in the C "
+                      f"oracle), {t:.1f} s"}
 
 
 def _progress(msg):
@@ -676,6 +753,9 @@ def main():
 
     # ---------------- CPU baseline: the oracle, on this host ----------------
     if not args.no_cpu_baseline:
+        if not args.no_modes:
+            _progress("mode cpu baselines (oracle) starting")
+            mode_cpu_baselines(result["modes"], args.cpu_seconds)
         _progress("cpu baseline (oracle) starting")
         from oracle import c_oracle, hlf_oracle
 

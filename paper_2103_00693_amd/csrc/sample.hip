@@ -87,6 +87,14 @@ __global__ __launch_bounds__(SampleShape<WMAX>::kThreads) void sample_kernel(
 // first), so accumulator register i of lane l holds output bit 8*(i/4) +
 // 4*(l/32) + i%4 of the column chunk for sample l % 32: a lane assembles 16
 // bits of its sample's word and takes the other 16 from lane l ^ 32.
+//
+// Parity without a conversion: the first K chunk adds its products to 2^23
+// (a constant accumulator operand) instead of 0, so every sum is 2^23 + c
+// with c <= r < 2^23 the count; fp32 holds it exactly with unit spacing, so
+// bit 0 of its raw bits is bit 0 of c, the GF(2) product.  The raw bits are
+// read with __float_as_uint on each element: __builtin_bit_cast applied to
+// an element of an ext_vector_type value read element 0 for every index in
+// this compiler (the generated IR extracted lane 0 sixteen times).
 // ---------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
@@ -95,6 +103,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int kMfmaMaxKC = HLF_MAX_N / 64;
 constexpr int kE2M1 = 4;         // operand format code of the instruction
 constexpr int kScaleOne = 127;   // E8M0 scale 2^0
+constexpr float kTwo23 = 8388608.0f;
 
 // JC column chunks (JC/2 words of every sample) per workgroup, WAVES waves.
 template <int JC, int WAVES>
@@ -137,6 +146,9 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
 #pragma unroll
     for (int q = 0; q < QW; ++q) l[q] = q < nq ? f.shift[w0 + q] : 0ull;
     const uint64_t lastmask = (r & 63) ? ((1ull << (r & 63)) - 1ull) : ~0ull;
+    v16f magic;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) magic[i] = kTwo23;
     // This workgroup's samples: a contiguous run of 32-sample blocks, taken by
     // its waves in turn (every SIMD of the CU gets the same number of blocks).
     const uint64_t nblk = (num + 31) >> 5;
@@ -171,12 +183,12 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
                 const v4i b4 = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * JC + jc) * 64 + lane) * 4]);
                 const v8i b = {b4[0], b4[1], b4[2], b4[3], 0, 0, 0, 0};
                 acc[jc] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                    b, a, first ? v16f{} : acc[jc], kE2M1, kE2M1, 0, kScaleOne, 0, kScaleOne);
+                    b, a, first ? magic : acc[jc], kE2M1, kE2M1, 0, kScaleOne, 0, kScaleOne);
             }
         };
         if (KC == 0) {
 #pragma unroll
-            for (int jc = 0; jc < JC; ++jc) acc[jc] = v16f{};
+            for (int jc = 0; jc < JC; ++jc) acc[jc] = magic;
         } else {
             auto ys = words(0);
             chunk(0, ys[0], true);
@@ -187,15 +199,15 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
                 if (2 * p + 1 < KC) chunk(2 * p + 1, ys[1], false);
             }
         }
-        // Register i holds the count of bit 8(i/4) + 4h + i%4: the low bytes of
-        // registers u, 4+u, 8+u, 12+u go to bytes 0..3 of one dword, whose
-        // bits 0 then move to bits 8t + u.
+        // Register i holds 2^23 + the count of bit 8(i/4) + 4h + i%4: the low
+        // bytes of registers u, 4+u, 8+u, 12+u go to bytes 0..3 of one dword,
+        // whose bits 0 then move to bits 8t + u.
         uint32_t word[JC];
 #pragma unroll
         for (int jc = 0; jc < JC; ++jc) {
             uint32_t c[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) c[i] = (uint32_t)acc[jc][i];
+            for (int i = 0; i < 16; ++i) c[i] = __float_as_uint(acc[jc][i]);
             uint32_t mine = 0;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
