@@ -386,6 +386,34 @@ hlf_status hlf_batch_graph_capture(hlf_batch b, const uint8_t *A_dev, int32_t ma
                                    const hlf_batch_params *params);
 hlf_status hlf_batch_graph_launch(hlf_batch b, hipStream_t stream);
 
+/* hlf_batch_reduce without a batch object, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * the allocator): the call allocates nothing and frees nothing.  Its scratch
+ * (work queue, chunk slots, layout offsets: about 832 KiB) is a device array
+ * of the library, one per GPU, kept until the process ends.  Every call on a
+ * GPU uses that GPU's array: calls that overlap on one GPU (on different
+ * streams) race and must be ordered by the caller.
+ *   count      instances, 1 .. 16384 (HLF_EINVAL beyond).
+ *   max_n      an upper bound of every n_i, 1 .. 192 (HLF_EINVAL otherwise).
+ *   n_dev      dev int32 [count]: n_i.  An entry outside [1, max_n] takes no
+ *              space in the layout and gets status HLF_EINVAL.
+ *   A_dev      dev uint8: the dense matrices concatenated, instance i at
+ *              byte offset sum_{k<i} n_k^2 (the layout of hlf_batch).
+ *   outputs    caller-owned device arrays in the layout of
+ *              hlf_batch_get_layout for these n_i: status_dev, rank_dev,
+ *              hash_dev [count]; pivots_dev, counts_dev [sum n_i];
+ *              basis_dev [sum n_i W_i]; shift_dev [sum W_i]; kernel_dev
+ *              [sum n_i W_i] or NULL.
+ *   params     NULL (chunk_log2 20, 8 waves per CU) or explicit.
+ * Results as hlf_batch_reduce; the same limits on max_rank and the chunk
+ * count apply (HLF_EINVAL).                                                    */
+hlf_status hlf_batch_reduce_noalloc(int32_t count, int32_t max_n, const int32_t *n_dev,
+                                    const uint8_t *A_dev, int32_t max_rank,
+                                    const hlf_batch_params *params, int32_t *status_dev,
+                                    int32_t *rank_dev, int32_t *pivots_dev, uint64_t *basis_dev,
+                                    uint64_t *shift_dev, uint64_t *kernel_dev,
+                                    uint64_t *counts_dev, uint64_t *hash_dev, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -282,6 +282,61 @@ __global__ void batch_queue_reset_kernel(QueueHead *q, ChunkSlot *slots, int cou
     }
 }
 
+// Offsets of the batch layout (prefix sums over the instance sizes) for the
+// allocation-free reduce: one workgroup of 1024 threads, count <= 1024 * kPer.
+// An n outside [1, max_n] counts as 0 (no space; its factor task reports
+// HLF_EINVAL).  n_eff receives the sizes the other kernels use.
+constexpr int kLayoutPer = 16;
+
+__global__ __launch_bounds__(1024) void noalloc_layout_kernel(const int32_t *__restrict__ n_in,
+                                                              int count, int max_n, int32_t *n_eff,
+                                                              int64_t *dense_off, int64_t *mat_off,
+                                                              int64_t *vec_off, int64_t *piv_off) {
+    __shared__ int64_t part[4][1024];
+    const int t = threadIdx.x;
+    const int i0 = t * kLayoutPer;
+    int64_t loc[4] = {0, 0, 0, 0};
+    for (int i = i0; i < min(count, i0 + kLayoutPer); ++i) {
+        const int n = n_in[i];
+        const int64_t ne = (n >= 1 && n <= max_n) ? n : 0;
+        const int64_t W = (ne + 63) >> 6;
+        loc[0] += ne * ne;
+        loc[1] += ne * W;
+        loc[2] += W;
+        loc[3] += ne;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[q][t] = loc[q];
+    __syncthreads();
+    // inclusive scan over the 1024 partial sums (Hillis-Steele)
+    for (int d = 1; d < 1024; d <<= 1) {
+        int64_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = t >= d ? part[q][t - d] : 0;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) part[q][t] += v[q];
+        __syncthreads();
+    }
+    int64_t run[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) run[q] = part[q][t] - loc[q];  // exclusive
+    for (int i = i0; i < min(count, i0 + kLayoutPer); ++i) {
+        const int n = n_in[i];
+        const int64_t ne = (n >= 1 && n <= max_n) ? n : 0;
+        const int64_t W = (ne + 63) >> 6;
+        n_eff[i] = (int32_t)ne;
+        dense_off[i] = run[0];
+        mat_off[i] = run[1];
+        vec_off[i] = run[2];
+        piv_off[i] = run[3];
+        run[0] += ne * ne;
+        run[1] += ne * W;
+        run[2] += W;
+        run[3] += ne;
+    }
+}
+
 __device__ __forceinline__ unsigned long long slot_base(ChunkSlot *slots, int s) {
     while (__builtin_amdgcn_readfirstlane(
                __hip_atomic_load(&slots[s].ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == 0)
@@ -339,7 +394,7 @@ __global__ __launch_bounds__(64) void batch_reduce_kernel(BatchDev b, const uint
         const int W = (n + 63) >> 6;
         const FactorOut out = record_of(b, (int)f);
         int r = -1;
-        if (W <= WMAX) {
+        if (n >= 1 && W <= WMAX) {
             const bool badv = wave_load_dense<WMAX>(A + b.dense_off[f], n, W, sm);
             r = factor_wave_core<WMAX>(n, W, badv, out, sm);
         } else if (lane == 0) {
@@ -495,16 +550,23 @@ bool params_ok(const hlf_batch_params &p) {
 // every instance with r <= max_rank claims max(1, 2^(r - chunk_log2)) chunks,
 // so the total over the batch must stay below 2^kClaimShift (else it would
 // carry into the slot field).
-bool claims_fit(const hlf_batch_s *b, int max_rank, int chunk_log2) {
+bool claims_fit_count(int count, int max_rank, int chunk_log2) {
     const int e = max_rank > chunk_log2 ? max_rank - chunk_log2 : 0;
     if (e >= hlf::kClaimShift) return false;
     const unsigned long long per = 1ull << e;
-    return (unsigned long long)b->count < ((1ull << hlf::kClaimShift) / per);
+    return (unsigned long long)count < ((1ull << hlf::kClaimShift) / per);
 }
 
+bool claims_fit(const hlf_batch_s *b, int max_rank, int chunk_log2) {
+    return claims_fit_count(b->count, max_rank, chunk_log2);
+}
+
+// Queue reset + the persistent factor/reduce kernel over the instances of a
+// device view, with the given queue and slot arrays.
 template <int WMAX>
-hlf_status launch_batch_reduce_t(hlf_batch_s *b, const uint8_t *A, int max_rank,
-                                 const hlf_batch_params &p, hipStream_t stream) {
+hlf_status launch_reduce_view(const hlf::BatchDev &d, const uint8_t *A, int max_rank,
+                              const hlf_batch_params &p, hlf::QueueHead *queue,
+                              hlf::ChunkSlot *slots, hipStream_t stream) {
     auto kern = hlf::batch_reduce_kernel<WMAX>;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0) != hipSuccess ||
@@ -512,13 +574,19 @@ hlf_status launch_batch_reduce_t(hlf_batch_s *b, const uint8_t *A, int max_rank,
         per_cu = 1;
     const int waves = std::min(p.waves_per_cu, per_cu);
     const int grid = hlf::device_cu_count() * waves;
-    const int reset_blocks = (b->count + 255) / 256;
+    const int reset_blocks = (d.count + 255) / 256;
     hipLaunchKernelGGL(hlf::batch_queue_reset_kernel, dim3(reset_blocks), dim3(256), 0, stream,
-                       b->queue, b->slots, b->count);
+                       queue, slots, d.count);
     if (hipGetLastError() != hipSuccess) return HLF_EDEVICE;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, stream, view_of(b), A, max_rank,
-                       p.chunk_log2, b->queue, b->slots);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, stream, d, A, max_rank, p.chunk_log2, queue,
+                       slots);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
+}
+
+template <int WMAX>
+hlf_status launch_batch_reduce_t(hlf_batch_s *b, const uint8_t *A, int max_rank,
+                                 const hlf_batch_params &p, hipStream_t stream) {
+    return launch_reduce_view<WMAX>(view_of(b), A, max_rank, p, b->queue, b->slots, stream);
 }
 
 hlf_status batch_reduce_impl(hlf_batch_s *b, const uint8_t *A, int max_rank,
@@ -958,6 +1026,94 @@ hlf_status hlf_batch_graph_capture(hlf_batch b, const uint8_t *A_dev, int32_t ma
 hlf_status hlf_batch_graph_launch(hlf_batch b, hipStream_t stream) {
     if (!b || !b->graph_exec) return HLF_EINVAL;
     return hipGraphLaunch(b->graph_exec, stream) == hipSuccess ? HLF_OK : HLF_EDEVICE;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free batched reduce.  Its scratch -- the work queue, the chunk
+// slots, the layout offsets and the checked sizes -- is one file-scope device
+// array; each device holds its own copy, located once per device with
+// hipGetSymbolAddress and used through that address only.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kNoAllocMaxCount = 16384;
+constexpr size_t kNoAllocQueueBytes = 256;
+constexpr size_t kNoAllocSlotBytes = sizeof(hlf::ChunkSlot) * kNoAllocMaxCount;
+constexpr size_t kNoAllocOffBytes = sizeof(int64_t) * kNoAllocMaxCount;
+constexpr size_t kNoAllocScratchBytes =
+    kNoAllocQueueBytes + kNoAllocSlotBytes + 4 * kNoAllocOffBytes + sizeof(int32_t) * kNoAllocMaxCount;
+static_assert(sizeof(hlf::QueueHead) <= kNoAllocQueueBytes, "queue head fits its space");
+static_assert(kNoAllocMaxCount <= 1024 * hlf::kLayoutPer, "one layout workgroup covers every instance");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+
+// Device address of this device's scratch array (looked up once per device).
+hlf_status scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HLF_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+            return HLF_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HLF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hlf_status hlf_batch_reduce_noalloc(int32_t count, int32_t max_n, const int32_t *n_dev,
+                                    const uint8_t *A_dev, int32_t max_rank,
+                                    const hlf_batch_params *params, int32_t *status_dev,
+                                    int32_t *rank_dev, int32_t *pivots_dev, uint64_t *basis_dev,
+                                    uint64_t *shift_dev, uint64_t *kernel_dev,
+                                    uint64_t *counts_dev, uint64_t *hash_dev, hipStream_t stream) {
+    if (count < 1 || count > kNoAllocMaxCount || max_n < 1 || max_n > 192) return HLF_EINVAL;
+    if (!n_dev || !A_dev || !status_dev || !rank_dev || !pivots_dev || !basis_dev || !shift_dev ||
+        !counts_dev || !hash_dev)
+        return HLF_EINVAL;
+    if (max_rank < 0 || max_rank > HLF_MAX_ENUM_RANK) return HLF_EINVAL;
+    const hlf_batch_params p = params ? *params : hlf_batch_params{20, 8};
+    if (!params_ok(p) || !claims_fit_count(count, max_rank, p.chunk_log2)) return HLF_EINVAL;
+    void *base = nullptr;
+    const hlf_status st = scratch_address(&base);
+    if (st != HLF_OK) return st;
+    unsigned char *sb = static_cast<unsigned char *>(base);
+    auto *queue = reinterpret_cast<hlf::QueueHead *>(sb);
+    auto *slots = reinterpret_cast<hlf::ChunkSlot *>(sb + kNoAllocQueueBytes);
+    auto *offs = reinterpret_cast<int64_t *>(sb + kNoAllocQueueBytes + kNoAllocSlotBytes);
+    auto *n_eff = reinterpret_cast<int32_t *>(offs + 4 * kNoAllocMaxCount);
+    hlf::BatchDev d;
+    d.count = count;
+    d.n = n_eff;
+    d.dense_off = offs;
+    d.mat_off = offs + kNoAllocMaxCount;
+    d.vec_off = offs + 2 * kNoAllocMaxCount;
+    d.piv_off = offs + 3 * kNoAllocMaxCount;
+    d.order = nullptr;
+    d.status = status_dev;
+    d.rank = rank_dev;
+    d.pivots = pivots_dev;
+    d.basis = basis_dev;
+    d.shift = shift_dev;
+    d.kernel = kernel_dev;
+    d.counts = counts_dev;
+    d.hash = hash_dev;
+    hipLaunchKernelGGL(hlf::noalloc_layout_kernel, dim3(1), dim3(1024), 0, stream, n_dev, count,
+                       max_n, n_eff, offs, offs + kNoAllocMaxCount, offs + 2 * kNoAllocMaxCount,
+                       offs + 3 * kNoAllocMaxCount);
+    if (hipGetLastError() != hipSuccess) return HLF_EDEVICE;
+    if (max_n <= 64) return launch_reduce_view<1>(d, A_dev, max_rank, p, queue, slots, stream);
+    return launch_reduce_view<3>(d, A_dev, max_rank, p, queue, slots, stream);
 }
 
 }  // extern "C"

@@ -38,7 +38,7 @@ EXPORTED = (
     "hlf_enumerate_reduce", "hlf_sample", "hlf_pair_stats", "hlf_membership",
     "hlf_batch_create", "hlf_batch_destroy", "hlf_batch_get_layout", "hlf_batch_factor_dense",
     "hlf_batch_enumerate", "hlf_batch_enumerate_overlap", "hlf_batch_solve", "hlf_batch_reduce", "hlf_batch_tune", "hlf_batch_graph_capture",
-    "hlf_batch_graph_launch",
+    "hlf_batch_graph_launch", "hlf_batch_reduce_noalloc",
 )
 
 
@@ -416,6 +416,8 @@ def _batch_lib():
         L.hlf_batch_graph_capture.argtypes = [vp, vp, i32, ctypes.POINTER(BatchParams)]
         L.hlf_batch_graph_launch.restype = i32
         L.hlf_batch_graph_launch.argtypes = [vp, vp]
+        L.hlf_batch_reduce_noalloc.restype = i32
+        L.hlf_batch_reduce_noalloc.argtypes = [i32, i32, vp, vp, i32, vp] + [vp] * 8 + [vp]
         _batch_sigs_done = True
     return L
 
@@ -586,3 +588,17 @@ class Batch:
         hashes = self._read("hash", 8 * self.count, np.uint64)
         return ([counts[int(self.piv_off[i]):int(self.piv_off[i]) + n] for i, n in enumerate(self.ns)],
                 [int(h) for h in hashes])
+
+
+def batch_reduce_noalloc(n_dev: torch.Tensor, max_n: int, A_dev: torch.Tensor, max_rank: int,
+                         out: dict, params: BatchParams | None = None, stream=None):
+    """hlf_batch_reduce_noalloc: factor + reduce of len(n_dev) instances into the
+    caller's arrays ``out`` (keys status, rank, pivots, basis, shift, kernel
+    (may be None), counts, hash; the layout of hlf_batch_get_layout)."""
+    p = ctypes.byref(params) if params is not None else None
+    k = out.get("kernel")
+    _check(_batch_lib().hlf_batch_reduce_noalloc(
+        int(n_dev.numel()), int(max_n), _ptr(n_dev), _ptr(A_dev), int(max_rank), p,
+        _ptr(out["status"]), _ptr(out["rank"]), _ptr(out["pivots"]), _ptr(out["basis"]),
+        _ptr(out["shift"]), _ptr(k) if k is not None else None, _ptr(out["counts"]),
+        _ptr(out["hash"]), _stream(stream)), "hlf_batch_reduce_noalloc")
