@@ -436,41 +436,47 @@ def batch_mode(hlf, torch, stream, dev):
 
 def serve_mode(torch):
     """Poisson arrivals of requests with N ~ U{4..32} (n = 16..1024), p = 0.5:
-    stage 1 + 65536 uniform samples, or the full enumeration when r <= 24.
-    Saturated throughput first (every request present at t = 0), then
-    arrival rates of 0.5, 0.8 and 0.95 of it; latency = arrival -> result in
-    host memory."""
+    stage 1 + 65536 uniform samples, or the full enumeration when r <= 24,
+    through the native server (8 slots).  Saturated throughput first (every
+    request present at t = 0), then arrival rates of 0.5, 0.8 and 0.95 of it,
+    2000 requests per point; latency = arrival -> result in pinned host
+    memory.  Results are released as they arrive."""
     from hlf_inputs import serve_requests
     from paper_2103_00693_amd.serve import Request, Server, percentile
 
-    count = 200
+    count = 2000
 
-    def reqs(rate, seed):
-        return [Request(rid=k, A=q["A"], seed=q["seed"], arrival=q["t"])
-                for k, q in enumerate(serve_requests(count, rate, master_seed=seed))]
+    def reqs(rate, seed, k=count):
+        return [Request(rid=i, A=q["A"], seed=q["seed"], arrival=q["t"])
+                for i, q in enumerate(serve_requests(k, rate, master_seed=seed))]
 
-    Server(slots=8).run(reqs(1000.0, 99), realtime=False)  # warm-up to steady state
-    srv = Server(slots=8)
+    srv = Server(slots=8, hbm_budget=1 << 30, host_budget=1 << 30)
+    srv.run(reqs(1000.0, 99, 300), realtime=False, keep_data=False)  # warm-up
+    sat_reqs = reqs(1000.0, 1)
     t0 = time.perf_counter()
-    res = srv.run(reqs(1000.0, 1), realtime=False)
+    res = srv.run(sat_reqs, realtime=False, keep_data=False)
     sat = count / (time.perf_counter() - t0)
     out = {"workload": "requests with N ~ U{4..32} (n = 16..1024), p = 0.5, diagonal Bernoulli(0.5): "
                        "stage 1 + 65536 uniform samples, or all 2^r solutions when r <= 24",
+           "server": "native (C++ worker thread, 8 HIP streams, 1 GiB device arena, pinned result arena)",
            "slots": 8, "requests_per_run": count,
            "saturated_requests_per_s": round(sat, 1),
            "kinds": {k: sum(1 for r in res if r.kind == k) for k in ("sample", "enumerate", "error")},
            "loads": []}
     for frac in (0.5, 0.8, 0.95):
-        srv = Server(slots=8)
-        t0 = time.perf_counter()
-        res = srv.run(reqs(frac * sat, 2), realtime=True)
-        wall = time.perf_counter() - t0
+        rq = reqs(frac * sat, 2)
+        res = srv.run(rq, realtime=True, keep_data=False)
         lat = [r.latency * 1e3 for r in res]
+        span = max(r.finished for r in res) - min(q.arrival for q in rq)
         out["loads"].append({"offered_fraction": frac, "offered_per_s": round(frac * sat, 1),
-                             "served_per_s": round(count / wall, 1),
+                             "served_per_s": round(count / span, 1),
                              "p50_ms": round(percentile(lat, 50), 3),
-                             "p99_ms": round(percentile(lat, 99), 3),
-                             "max_in_flight_bytes": srv.max_in_flight})
+                             "p99_ms": round(percentile(lat, 99), 3)})
+    st = srv.stats()
+    out["hbm_arena_bytes"] = st["hbm_bytes"]
+    out["hbm_peak_bytes"] = st["hbm_peak_bytes"]
+    out["cache_hits"] = st["cache_hits"]
+    srv.close()
     return out
 
 

@@ -386,6 +386,91 @@ hlf_status hlf_batch_graph_capture(hlf_batch b, const uint8_t *A_dev, int32_t ma
                                    const hlf_batch_params *params);
 hlf_status hlf_batch_graph_launch(hlf_batch b, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous admission of single-instance requests (Section 1's
+ * problem per request: stage 1, then every solution when 2^r is small --
+ * the traversal of Section 2 -- or uniform samples, the output distribution
+ * of Appendix A).  A server owns a worker thread, `slots` HIP streams, one
+ * device arena of hbm_bytes (every device byte the server uses: inputs,
+ * packed rows, stage-1 records, outputs and the stage-1 cache) and one pinned
+ * host arena of host_bytes for results.  A request is admitted when its
+ * arrival time has passed, a slot is free and its stage-1 memory (input,
+ * packed rows, record) can be carved from the arena; its phases then run on
+ * the slot's stream, and once r is known its output is carved at its exact
+ * size (the request waits while the arena or the result arena is full).  A
+ * request's result depends only on (A, seed).
+ * ------------------------------------------------------------------------- */
+typedef struct hlf_server_s *hlf_server;
+
+typedef struct hlf_server_config {
+    int32_t slots;          /* concurrent requests (HIP streams), 1 .. 64           */
+    int64_t hbm_bytes;      /* device arena, >= 1 MiB                               */
+    int64_t host_bytes;     /* pinned result arena, >= 1 MiB                        */
+    int32_t num_samples;    /* samples per sampling request, >= 1                   */
+    int32_t enum_max_rank;  /* all solutions when n <= 64 and r <= this (0 .. 30)    */
+    int32_t cache_entries;  /* stage-1 records kept (LRU), 0 = no cache              */
+} hlf_server_config;
+
+typedef struct hlf_request {
+    int64_t id;             /* caller's tag, returned in the result                 */
+    int32_t n;              /* 1 .. HLF_MAX_N                                       */
+    const uint8_t *A;       /* host [n*n] row-major 0/1, read at admission: it must
+                               stay valid until the request's result is polled   */
+    uint64_t seed;          /* sampling seed (hlf_sample's stream)                  */
+    uint64_t key[2];        /* stage-1 cache key (a digest of A); {0,0}: no caching */
+    int64_t arrival_ns;     /* not admitted before this time of hlf_server_now      */
+} hlf_request;
+
+typedef struct hlf_result {
+    int64_t id;
+    int32_t status;         /* hlf_status: HLF_OK, HLF_ENOTSYM, HLF_ENOMEM, ...      */
+    int32_t n, rank;
+    int32_t kind;           /* 1: all solutions, 2: samples, 0: error (no data)      */
+    int32_t word_bytes;     /* bytes per solution: 2/4/8 (kind 1), 8*W (kind 2)      */
+    int64_t count;          /* solutions in data                                    */
+    const void *data;       /* pinned host memory of the server, valid until
+                               hlf_server_release(data)                             */
+    int64_t arrival_ns, admitted_ns, finished_ns;  /* server clock                  */
+    int32_t cache_hit;
+} hlf_result;
+
+typedef struct hlf_server_stats {
+    int64_t admitted, completed, cache_hits;
+    int64_t hbm_bytes;       /* the arena                                           */
+    int64_t hbm_peak_bytes;  /* most arena bytes in use at once                     */
+    int64_t host_peak_bytes; /* most pinned result bytes in use at once             */
+    int32_t worker_status;   /* HLF_OK, or the first HIP failure of the worker      */
+} hlf_server_stats;
+
+/* Create a server on the current device (allocates its arenas and streams and
+ * starts its worker).  HLF_EINVAL for a bad configuration, HLF_ENOMEM if an
+ * arena cannot be allocated.                                                  */
+hlf_status hlf_server_create(const hlf_server_config *cfg, hlf_server *out);
+
+/* Nanoseconds since the server was created (its clock for arrival times).     */
+int64_t hlf_server_now(hlf_server s);
+
+/* Queue `count` requests (the request records are copied; each A is read
+ * when its request is admitted).  Requests are admitted in submission order.  HLF_EINVAL for n outside
+ * [1, HLF_MAX_N] or a NULL A (nothing is queued then).  A request whose
+ * worst-case memory exceeds the arena completes with HLF_ENOMEM.              */
+hlf_status hlf_server_submit(hlf_server s, const hlf_request *reqs, int32_t count);
+
+/* Move up to `max` finished results to out (completion order), waiting up to
+ * wait_ms for the first; *got receives the number moved.                      */
+hlf_status hlf_server_poll(hlf_server s, hlf_result *out, int32_t max, int32_t *got,
+                           int32_t wait_ms);
+
+/* Return a result's pinned memory to the server.  Results that are never
+ * released fill the host arena, and requests then wait for memory.           */
+hlf_status hlf_server_release(hlf_server s, const void *data);
+
+hlf_status hlf_server_get_stats(hlf_server s, hlf_server_stats *out);
+
+/* Stop admitting, finish the requests in flight, free everything (the pinned
+ * result memory included).  NULL is accepted.                                 */
+hlf_status hlf_server_destroy(hlf_server s);
+
 /* hlf_batch_reduce without a batch object, for callers that cannot allocate
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * the allocator): the call allocates nothing and frees nothing.  Its scratch

@@ -19,7 +19,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhlf.so")
 
 SOURCES = ["factor.hip", "enumerate.hip", "sample.hip", "verify.hip", "batch.hip", "solve.hip",
-           "hlf_abi.cpp"]
+           "hlf_abi.cpp", "serve.cpp"]
 
 ARCH = os.environ.get("HLF_OFFLOAD_ARCH", "gfx950")
 

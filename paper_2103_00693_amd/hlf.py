@@ -39,6 +39,8 @@ EXPORTED = (
     "hlf_batch_create", "hlf_batch_destroy", "hlf_batch_get_layout", "hlf_batch_factor_dense",
     "hlf_batch_enumerate", "hlf_batch_enumerate_overlap", "hlf_batch_solve", "hlf_batch_reduce", "hlf_batch_tune", "hlf_batch_graph_capture",
     "hlf_batch_graph_launch", "hlf_batch_reduce_noalloc",
+    "hlf_server_create", "hlf_server_now", "hlf_server_submit", "hlf_server_poll", "hlf_server_release",
+    "hlf_server_get_stats", "hlf_server_destroy",
 )
 
 

@@ -1,47 +1,46 @@
-"""Serving loop: continuous admission of HLF requests onto one GPU.
+"""Serving: continuous admission of HLF requests onto one GPU, through the
+native server of libhlf.so (hlf_server_*).
 
 A request carries a dense matrix A (any n <= 1024) and a seed.  Its work is
 the paper's two stages (Sections 1-2): stage 1 (pack + factor), then either
-the full enumeration of its 2^r solutions when r <= ``enum_max_rank`` and
-n <= 64, or ``num_samples`` uniform solutions (the quantum circuit's output
-distribution, Appendix A).  Results are copied to pinned host memory.
+all 2^r solutions when r <= ``enum_max_rank`` and n <= 64, or
+``num_samples`` uniform solutions (the quantum circuit's output distribution,
+Appendix A).
 
-Scheduling.  The server owns ``slots`` HIP streams.  A request is admitted
-when a slot is free and its worst-case device footprint fits the HBM budget;
-admitted requests advance independently (phase 1 -> phase 2 -> copy-out),
-each phase enqueued on the slot's stream as soon as the previous one has
-finished, so requests that arrive while others run are admitted as slots and
-memory free up and their kernels overlap on the device.  Every result depends
-only on (A, seed): the sampling stream is keyed by (seed, sample index), never
-by slot or timing, so a request's result is bit-identical alone and in a mix.
+The server (C++, one worker thread) owns ``slots`` HIP streams, one device
+arena of ``hbm_budget`` bytes holding every device byte it uses (inputs,
+packed rows, stage-1 records, outputs, the stage-1 cache) and a pinned host
+arena for results.  A request is admitted when its arrival time has passed, a
+slot is free and its stage-1 memory fits the arena; its phases then run on the
+slot's stream (its output is carved at its exact size once r is known), so
+requests arriving while others run are admitted as slots and memory free up
+and their kernels overlap on the device.  Every result depends only on
+(A, seed).
 
-Stage-1 records are cached on the device, keyed by a digest of A (LRU, part
-of the budget); a repeated matrix skips stage 1.
-
-All device work goes through the C ABI of libhlf.so (``hlf``); this module only
-schedules.
+This module only marshals: it submits requests (with an xxh3 digest of A as
+the stage-1 cache key) and wraps finished results as numpy views of the
+server's pinned memory, returned to the server when the view is dropped.
 """
 
 from __future__ import annotations
 
-import collections
+import ctypes
 import hashlib
 import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import hlf
 
 try:  # a fast 128-bit digest for the stage-1 cache key; blake2b otherwise
     import xxhash
 
-    def _digest(buf: bytes) -> bytes:
+    def _digest(buf) -> bytes:
         return xxhash.xxh3_128_digest(buf)
 except ImportError:  # pragma: no cover
-    def _digest(buf: bytes) -> bytes:
+    def _digest(buf) -> bytes:
         return hashlib.blake2b(buf, digest_size=16).digest()
-from dataclasses import dataclass, field
-
-import numpy as np
-import torch
-
-from . import hlf
 
 
 @dataclass
@@ -59,44 +58,86 @@ class Result:
     n: int
     rank: int
     kind: str                      # "enumerate" | "sample" | "error"
-    data: np.ndarray | None        # host result (pinned memory): uint64 (count, W) or narrow words
-    admitted: float = 0.0
+    data: np.ndarray | None        # pinned host memory of the server, or None
+    admitted: float = 0.0          # seconds from the start of the run
     finished: float = 0.0
     latency: float = 0.0           # finished - arrival
     cache_hit: bool = False
 
 
-@dataclass
-class _Entry:  # device-resident stage-1 record in the cache
-    F: hlf.Factors
-    rank: int
-    status: int
-    nbytes: int
+class _Config(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("hbm_bytes", ctypes.c_int64), ("host_bytes", ctypes.c_int64),
+                ("num_samples", ctypes.c_int32), ("enum_max_rank", ctypes.c_int32),
+                ("cache_entries", ctypes.c_int32)]
 
 
-@dataclass
-class _Active:
-    req: Request
-    slot: int
-    phase: int
-    n: int
-    footprint: int
-    admitted: float
-    F: hlf.Factors | None = None
-    out: torch.Tensor | None = None
-    host_out: torch.Tensor | None = None
-    event: torch.cuda.Event | None = None
-    key: bytes = b""
-    cache_hit: bool = False
-    kind: str = ""
-    rank: int = -1
-    status: int = 0
-    extra: dict = field(default_factory=dict)
+class _Request(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("n", ctypes.c_int32), ("A", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64), ("key", ctypes.c_uint64 * 2), ("arrival_ns", ctypes.c_int64)]
 
 
-def _record_bytes(n: int) -> int:
-    W = hlf.words_for(n)
-    return 8 * (2 * n * W + W) + 4 * (n + 2)
+class _Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("rank", ctypes.c_int32), ("kind", ctypes.c_int32), ("word_bytes", ctypes.c_int32),
+                ("count", ctypes.c_int64), ("data", ctypes.c_void_p), ("arrival_ns", ctypes.c_int64),
+                ("admitted_ns", ctypes.c_int64), ("finished_ns", ctypes.c_int64),
+                ("cache_hit", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("admitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("cache_hits", ctypes.c_int64),
+                ("hbm_bytes", ctypes.c_int64), ("hbm_peak_bytes", ctypes.c_int64),
+                ("host_peak_bytes", ctypes.c_int64), ("worker_status", ctypes.c_int32)]
+
+
+_sigs = False
+
+
+def _lib():
+    global _sigs
+    L = hlf.lib()
+    if not _sigs:
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.hlf_server_create.restype = i32
+        L.hlf_server_create.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(vp)]
+        L.hlf_server_now.restype = i64
+        L.hlf_server_now.argtypes = [vp]
+        L.hlf_server_submit.restype = i32
+        L.hlf_server_submit.argtypes = [vp, ctypes.POINTER(_Request), i32]
+        L.hlf_server_poll.restype = i32
+        L.hlf_server_poll.argtypes = [vp, ctypes.POINTER(_Result), i32, ctypes.POINTER(i32), i32]
+        L.hlf_server_release.restype = i32
+        L.hlf_server_release.argtypes = [vp, vp]
+        L.hlf_server_get_stats.restype = i32
+        L.hlf_server_get_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+        L.hlf_server_destroy.restype = i32
+        L.hlf_server_destroy.argtypes = [vp]
+        _sigs = True
+    return L
+
+
+class _Lease:
+    """Returns a result's pinned memory to the server when dropped."""
+
+    def __init__(self, server: "Server", ptr: int):
+        self.server = server
+        self.ptr = ptr
+
+    def __del__(self):
+        h = getattr(self.server, "_h", None)
+        if h:
+            _lib().hlf_server_release(h, ctypes.c_void_p(self.ptr))
+
+
+def _view(server: "Server", r: _Result) -> np.ndarray:
+    nbytes = int(r.count) * int(r.word_bytes)
+    buf = (ctypes.c_uint8 * nbytes).from_address(r.data)
+    buf._lease = _Lease(server, r.data)  # the numpy view keeps buf, buf keeps the lease
+    if r.kind == 1:
+        dt = {2: np.int16, 4: np.int32, 8: np.int64}[int(r.word_bytes)]
+        return np.frombuffer(buf, dtype=dt)
+    W = int(r.word_bytes) // 8
+    return np.frombuffer(buf, dtype=np.int64).reshape(int(r.count), W)
 
 
 def _worst_output_bytes(n: int, num_samples: int, enum_max_rank: int) -> int:
@@ -108,187 +149,106 @@ def _worst_output_bytes(n: int, num_samples: int, enum_max_rank: int) -> int:
     return sample
 
 
+def _record_bytes(n: int) -> int:
+    W = hlf.words_for(n)
+    return (8 + 4 * n + 7) // 8 * 8 + 8 * (n * W + W)
+
+
 class Server:
     def __init__(self, slots: int = 8, hbm_budget: int = 1 << 30, num_samples: int = 65536,
-                 enum_max_rank: int = 24, cache_entries: int = 256, device: int = 0):
-        self.device = torch.device("cuda", device)
+                 enum_max_rank: int = 24, cache_entries: int = 256, host_budget: int = 512 << 20):
         self.slots = slots
         self.budget = hbm_budget
         self.num_samples = num_samples
         self.enum_max_rank = enum_max_rank
-        self.cache_entries = cache_entries
-        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
-        # Per-slot buffers, grown on demand and reused: a slot takes its next
-        # request only after every event of the previous one has fired.
-        # Pinned staging of the dense input, its device copy, the packed rows,
-        # the stage-2 output, and the pinned (status, rank) pair.
-        self.staging: list[torch.Tensor | None] = [None] * slots
-        self.dev_A: list[torch.Tensor | None] = [None] * slots
-        self.dev_rows: list[torch.Tensor | None] = [None] * slots
-        self.dev_out: list[torch.Tensor | None] = [None] * slots
-        self.head_host = [torch.empty(2, dtype=torch.int32, pin_memory=True) for _ in range(slots)]
-        self.cache: collections.OrderedDict[bytes, _Entry] = collections.OrderedDict()
-        self.cache_bytes = 0
-        self.in_flight = 0
-        self.max_in_flight = 0
-        self.stats = {"admitted": 0, "cache_hits": 0, "rejected": 0}
+        cfg = _Config(slots, hbm_budget, host_budget, num_samples, enum_max_rank, cache_entries)
+        h = ctypes.c_void_p()
+        hlf._check(_lib().hlf_server_create(ctypes.byref(cfg), ctypes.byref(h)), "hlf_server_create")
+        self._h = h
 
-    # -- footprint / budget -------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().hlf_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
     def footprint(self, n: int) -> int:
+        """Most device bytes one request of size n can hold at once: input,
+        packed rows and record in stage 1, then record and output (an upper
+        bound; the arena rounds blocks to 256 bytes)."""
         return n * n + 8 * n * hlf.words_for(n) + _record_bytes(n) + _worst_output_bytes(
             n, self.num_samples, self.enum_max_rank)
 
-    def _fits(self, nbytes: int) -> bool:
-        return self.in_flight + self.cache_bytes + nbytes <= self.budget
+    def stats(self) -> dict:
+        st = _Stats()
+        hlf._check(_lib().hlf_server_get_stats(self._h, ctypes.byref(st)), "hlf_server_get_stats")
+        return {k: getattr(st, k) for k, _ in _Stats._fields_}
 
-    def _evict_for(self, nbytes: int):
-        while self.cache and not self._fits(nbytes):
-            _, e = self.cache.popitem(last=False)
-            self.cache_bytes -= e.nbytes
+    @property
+    def max_in_flight(self) -> int:
+        """Most device arena bytes in use at once (inputs, records, outputs, cache)."""
+        return int(self.stats()["hbm_peak_bytes"])
 
-    # -- phases ---------------------------------------------------------------
-    def _admit(self, req: Request, slot: int, now: float) -> _Active:
-        n = req.A.shape[0]
-        a = _Active(req=req, slot=slot, phase=1, n=n, footprint=self.footprint(n), admitted=now)
-        A = np.ascontiguousarray(req.A, dtype=np.uint8)
-        a.key = _digest(A.data) + n.to_bytes(2, "little")
-        self.in_flight += a.footprint
-        self.max_in_flight = max(self.max_in_flight, self.in_flight + self.cache_bytes)
-        self.stats["admitted"] += 1
-        s = self.streams[slot]
-        hit = self.cache.get(a.key)
-        if hit is not None:
-            self.cache.move_to_end(a.key)
-            a.cache_hit = True
-            self.stats["cache_hits"] += 1
-            a.F, a.rank, a.status = hit.F, hit.rank, hit.status
-            a.F._buf.record_stream(s)  # keep the memory until this stream is done with it
-            self._launch_phase2(a)
-            return a
-        with torch.cuda.stream(s):
-            # H2D through the slot's pinned staging buffer.
-            st = self._grow(self.staging, slot, n * n, torch.uint8, pinned=True)
-            st[: n * n].numpy()[:] = A.reshape(-1)
-            Ad = self._grow(self.dev_A, slot, n * n, torch.uint8)[: n * n]
-            Ad.copy_(st[: n * n], non_blocking=True)
-            W = hlf.words_for(n)
-            rows = self._grow(self.dev_rows, slot, n * W, torch.int64)[: n * W].view(n, W)
-            # The record outlives the request when it is cached: its own buffer.
-            a.F = hlf.Factors.packed(n, device=self.device)
-            # pack writes its verdict into the record's status; the factor
-            # keeps a failed one (HLF_FACTOR_PACK_STATUS)
-            hlf.pack_dense(Ad.view(n, n), rows, a.F.status, stream=s)
-            hlf.factor(rows, n, a.F, stream=s, pack_status=True)
-            self.head_host[slot].copy_(a.F.status_rank, non_blocking=True)
-            a.event = torch.cuda.Event()
-            a.event.record(s)
-        return a
-
-    def _grow(self, pool, slot: int, numel: int, dtype, pinned: bool = False) -> torch.Tensor:
-        buf = pool[slot]
-        if buf is None or buf.numel() < numel:
-            size = max(numel, 1 << 16)
-            if pinned:
-                buf = torch.empty(size, dtype=dtype, pin_memory=True)
-            else:
-                buf = torch.empty(size, dtype=dtype, device=self.device)
-            pool[slot] = buf
-        return buf
-
-    def _launch_phase2(self, a: _Active):
-        a.phase = 2
-        s = self.streams[a.slot]
-        n, r = a.n, a.rank
-        with torch.cuda.stream(s):
-            if a.status != hlf.HLF_OK:
-                a.kind = "error"
-                a.out = None
-            elif r <= self.enum_max_rank and n <= 64:
-                a.kind = "enumerate"
-                wb = 16 if n <= 16 else 32 if n <= 32 else 64
-                dt = {16: torch.int16, 32: torch.int32, 64: torch.int64}[wb]
-                nbytes = (1 << r) * wb // 8
-                out = self._grow(self.dev_out, a.slot, (nbytes + 7) // 8, torch.int64)
-                a.out = out.view(torch.uint8)[:nbytes].view(dt)
-                hlf.enumerate_solutions(a.F, 0, 1 << r, wb, out=a.out, stream=s)
-            else:
-                a.kind = "sample"
-                W = a.F.words
-                out = self._grow(self.dev_out, a.slot, self.num_samples * W, torch.int64)
-                a.out = out[: self.num_samples * W].view(self.num_samples, W)
-                hlf.sample(a.F, a.req.seed, self.num_samples, out=a.out, stream=s)
-            if a.out is not None:
-                a.host_out = torch.empty(a.out.shape, dtype=a.out.dtype, pin_memory=True)
-                a.host_out.copy_(a.out, non_blocking=True)
-            a.event = torch.cuda.Event()
-            a.event.record(s)
-
-    def _finish(self, a: _Active, now: float) -> Result:
-        self.in_flight -= a.footprint
-        if not a.cache_hit and a.status == hlf.HLF_OK and self.cache_entries > 0:
-            nb = _record_bytes(a.n)
-            self._evict_for(nb)
-            if self._fits(nb):
-                self.cache[a.key] = _Entry(a.F, a.rank, a.status, nb)
-                self.cache_bytes += nb
-                while len(self.cache) > self.cache_entries:
-                    _, e = self.cache.popitem(last=False)
-                    self.cache_bytes -= e.nbytes
-        # The pinned buffer itself is handed over (numpy keeps it alive).
-        data = a.host_out.numpy() if a.host_out is not None else None
-        arrival = a.req.arrival if self._realtime else 0.0
-        return Result(rid=a.req.rid, status=a.status, n=a.n, rank=a.rank, kind=a.kind, data=data,
-                      admitted=a.admitted, finished=now, latency=now - arrival,
-                      cache_hit=a.cache_hit)
-
-    # -- the loop ---------------------------------------------------------------
-    def run(self, requests, realtime: bool = True) -> list[Result]:
+    def run(self, requests, realtime: bool = True, keep_data: bool = True,
+            stall_s: float = 60.0) -> list[Result]:
         """Serve `requests` (arrival times in seconds from the start when
-        `realtime`, else all present at time 0) and return their results in
-        completion order."""
-        pending = collections.deque(sorted(requests, key=lambda q: (q.arrival, q.rid)))
-        for q in pending:
-            if self.footprint(q.A.shape[0]) > self.budget:
-                raise hlf.HlfError(hlf.HLF_ENOMEM, f"request {q.rid} exceeds the HBM budget")
-        self._realtime = realtime  # without it every request counts as arrived at t = 0
-        active: dict[int, _Active] = {}
-        free = list(range(self.slots))
+        `realtime`, else all present at the start) and return their results
+        in completion order.  With keep_data=False each result's memory goes
+        back to the server as soon as it is polled (data is None)."""
+        L = _lib()
+        reqs = sorted(requests, key=lambda q: (q.arrival, q.rid))
+        mats = [np.ascontiguousarray(q.A, dtype=np.uint8) for q in reqs]
+        arr = (_Request * max(len(reqs), 1))()
+        for k, (q, A) in enumerate(zip(reqs, mats)):
+            d = _digest(A.data)
+            arr[k].id = q.rid
+            arr[k].n = A.shape[0]
+            arr[k].A = A.ctypes.data
+            arr[k].seed = q.seed & ((1 << 64) - 1)
+            arr[k].key[0] = int.from_bytes(d[:8], "little")
+            arr[k].key[1] = int.from_bytes(d[8:16], "little")
+        # the run's clock starts once everything is prepared (1 ms to submit)
+        start = L.hlf_server_now(self._h) + 1_000_000
+        arrival = {}
+        for k, q in enumerate(reqs):
+            t = start + (int(q.arrival * 1e9) if realtime else 0)
+            arr[k].arrival_ns = t
+            arrival[q.rid] = t
+        if reqs:
+            hlf._check(L.hlf_server_submit(self._h, arr, len(reqs)), "hlf_server_submit")
+        out = (_Result * 64)()
+        got = ctypes.c_int32()
         done: list[Result] = []
-        t0 = time.perf_counter()
-        while pending or active:
-            now = time.perf_counter() - t0
-            progressed = False
-            # admission: arrived requests, free slots, budget (with cache eviction)
-            while pending and free and (not realtime or pending[0].arrival <= now):
-                fp = self.footprint(pending[0].A.shape[0])
-                if not self._fits(fp):
-                    self._evict_for(fp)
-                    if not self._fits(fp):
-                        break
-                req = pending.popleft()
-                slot = free.pop()
-                active[slot] = self._admit(req, slot, now)
-                progressed = True
-            # advance admitted requests whose last phase finished
-            for slot in list(active):
-                a = active[slot]
-                if a.event is not None and not a.event.query():
-                    continue
-                now = time.perf_counter() - t0
-                if a.phase == 1:
-                    head = self.head_host[slot]
-                    a.status, a.rank = int(head[0]), int(head[1])
-                    self._launch_phase2(a)
-                else:
-                    done.append(self._finish(a, now))
-                    del active[slot]
-                    free.append(slot)
-                progressed = True
-            if not progressed:
-                if active:
-                    time.sleep(0)
-                elif pending and realtime:
-                    time.sleep(max(0.0, min(1e-3, pending[0].arrival - now)))
+        last = time.perf_counter()
+        while len(done) < len(reqs):
+            hlf._check(L.hlf_server_poll(self._h, out, 64, ctypes.byref(got), 50), "hlf_server_poll")
+            if got.value == 0:
+                if time.perf_counter() - last > stall_s:
+                    # the server reads each A at admission: stop it before `mats` goes away
+                    msg = f"server made no progress for {stall_s} s ({len(done)}/{len(reqs)} done): {self.stats()}"
+                    self.close()
+                    raise hlf.HlfError(hlf.HLF_EDEVICE, msg)
+                continue
+            last = time.perf_counter()
+            for i in range(got.value):
+                r = out[i]
+                data = None
+                if r.data:
+                    if keep_data:
+                        data = _view(self, r)
+                    else:
+                        L.hlf_server_release(self._h, ctypes.c_void_p(r.data))
+                kind = {1: "enumerate", 2: "sample"}.get(int(r.kind), "error")
+                t_arr = arrival[int(r.id)]
+                done.append(Result(rid=int(r.id), status=int(r.status), n=int(r.n), rank=int(r.rank),
+                                   kind=kind, data=data, admitted=(r.admitted_ns - start) * 1e-9,
+                                   finished=(r.finished_ns - start) * 1e-9,
+                                   latency=(r.finished_ns - t_arr) * 1e-9, cache_hit=bool(r.cache_hit)))
         return done
 
 

@@ -149,3 +149,22 @@ def test_host_detected_errors_of_solve_dense():
     # a NULL record member
     bad = _rec(20, "basis")
     assert L.hlf_solve_dense(p, ctypes.byref(bad), 0, 8, 32, p, None) == hlf.HLF_EINVAL
+
+
+def test_server_rejects_bad_configurations_on_the_host():
+    from paper_2103_00693_amd import serve
+
+    L = serve._lib()
+    h = ctypes.c_void_p()
+    for bad in (dict(slots=0), dict(slots=65), dict(hbm_bytes=1000), dict(host_bytes=1000),
+                dict(num_samples=0), dict(enum_max_rank=31), dict(cache_entries=-1)):
+        cfg = dict(slots=2, hbm_bytes=1 << 24, host_bytes=1 << 24, num_samples=16, enum_max_rank=10,
+                   cache_entries=4)
+        cfg.update(bad)
+        c = serve._Config(cfg["slots"], cfg["hbm_bytes"], cfg["host_bytes"], cfg["num_samples"],
+                          cfg["enum_max_rank"], cfg["cache_entries"])
+        assert L.hlf_server_create(ctypes.byref(c), ctypes.byref(h)) == hlf.HLF_EINVAL, bad
+    assert L.hlf_server_create(None, ctypes.byref(h)) == hlf.HLF_EINVAL
+    assert L.hlf_server_submit(None, None, 0) == hlf.HLF_EINVAL
+    assert L.hlf_server_destroy(None) == hlf.HLF_OK
+    assert L.hlf_server_now(None) == -1
