@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--no-modes", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--only", default="",
                     help="comma-separated secondary modes to run (reduce, sample, tiny, steady, batch, "
-                         "general, verify, serve); default all")
+                         "general, circuit, verify, serve); default all")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (for HBM counter scaling)")
     return ap.parse_args()
@@ -304,6 +304,71 @@ def general_mode(hlf, torch, stream, dev):
                       "solutions_per_s_G": round(count / sec / 1e9, 3)}
     F.check()
     out["low_rank"] = res
+    del buf
+    return out
+
+
+def circuit_mode(hlf, torch, stream, dev):
+    """The paper's circuit evaluated literally (Section 2, Eqs. (1)-(2),
+    Fig. 1(c)) in the FPGA's counter order (Section 4): (a) the N=5 workload,
+    all 2^r solutions of each of the 8 seeds as uint32, one launch per seed,
+    beside the Gray-order materialise of the same instances with the same
+    launches; (b) a 32 x 32 grid subgraph with 10 edges and 4 coloured
+    vertices (n = 1024, r = 24): all 2^24 solutions as 16-word vectors."""
+    from hlf_inputs import CONFIG2_SEEDS, grid_instance, sparse_grid_instance
+
+    out = {}
+    Fs, rows = [], []
+    for s in CONFIG2_SEEDS:
+        A = torch.from_numpy(grid_instance(5, seed=s)).to(dev)
+        r_, _ = hlf.pack_dense(A, stream=stream)
+        Fs.append(hlf.factor(r_, 25, stream=stream))
+        rows.append(r_)
+    stream.synchronize()
+    ranks = [int(F.rank.item()) for F in Fs]
+    outs = [torch.empty(1 << r, dtype=torch.int32, device=dev) for r in ranks]
+
+    def circ():
+        for F, r_, o, rk in zip(Fs, rows, outs, ranks):
+            hlf.enumerate_circuit(F, r_, 5, 0, 1 << rk, 32, out=o, stream=stream)
+
+    def gray():
+        for F, o, rk in zip(Fs, outs, ranks):
+            hlf.enumerate_solutions(F, 0, 1 << rk, 32, out=o, stream=stream)
+
+    nbytes = 4 * sum(1 << r for r in ranks)
+    res = {"workload": "N=5 grid (n=25), all edges, seeds 0-7: all 2^r solutions as uint32, one launch per seed",
+           "ranks": ranks, "bytes": nbytes, "kernel": "circuit_tile_kernel<uint32_t>"}
+    for name, fn in (("circuit", circ), ("gray_tile_algebra", gray)):
+        sec = _timed(torch, stream, fn, 10)
+        res[name] = {"us": round(sec * 1e6, 2), "achieved_GBs": round(nbytes / sec / 1e9, 1),
+                     "frac_of_8TBs": round(nbytes / sec / 8e12, 4),
+                     "solutions_per_s_G": round(nbytes / 4 / sec / 1e9, 2)}
+    for F in Fs:
+        F.check()
+    out["n25"] = res
+    del outs
+    A = sparse_grid_instance(32, 10, 0, 4)
+    Ad = torch.from_numpy(A).to(dev)
+    r_, _ = hlf.pack_dense(Ad, stream=stream)
+    F = hlf.factor(r_, 1024, stream=stream)
+    stream.synchronize()
+    F.check()
+    r = int(F.rank.item())
+    count = 1 << r
+    buf = torch.empty((count, 16), dtype=torch.int64, device=dev)
+    nbytes = count * 128
+    res = {"workload": "32x32 grid subgraph, 10 edges, 4 coloured vertices (n=1024): all 2^r solutions "
+                       "as 16 uint64 words", "rank": r, "bytes": nbytes, "kernel": "circuit_wide_kernel<16>"}
+    for name, fn in (("circuit", lambda: hlf.enumerate_circuit(F, r_, 32, 0, count, 1024, out=buf, stream=stream)),
+                     ("counter_tile_algebra", lambda: hlf.enumerate_solutions(F, 0, count, 1024, out=buf,
+                                                                              stream=stream, order="counter"))):
+        sec = _timed(torch, stream, fn, 3)
+        res[name] = {"ms": round(sec * 1e3, 3), "achieved_GBs": round(nbytes / sec / 1e9, 1),
+                     "frac_of_8TBs": round(nbytes / sec / 8e12, 4),
+                     "solutions_per_s_G": round(count / sec / 1e9, 3)}
+    F.check()
+    out["n1024"] = res
     del buf
     return out
 
@@ -749,6 +814,7 @@ def main():
                          ("steady", lambda: steady_mode(hlf, torch, stream, dev)),
                          ("batch", lambda: batch_mode(hlf, torch, stream, dev)),
                          ("general", lambda: general_mode(hlf, torch, stream, dev)),
+                         ("circuit", lambda: circuit_mode(hlf, torch, stream, dev)),
                          ("verify", lambda: verify_mode(hlf, torch, stream, dev)),
                          ("serve", lambda: serve_mode(torch))):
             if only and name not in only:

@@ -28,6 +28,7 @@ __all__ = [
     "grid_instance",
     "paper_diagonal",
     "random_symmetric",
+    "sparse_grid_instance",
     "batch_instances",
     "serve_requests",
     "CONFIG2_SEEDS",
@@ -97,6 +98,21 @@ def grid_instance(N: int, p: float = 1.0, seed: int | None = None,
             A[u, v] = 1
             A[v, u] = 1
     A[np.arange(n), np.arange(n)] = bvec
+    return A
+
+
+def sparse_grid_instance(N: int, edges: int, seed: int, loops: int = 0) -> np.ndarray:
+    """An N x N grid subgraph with `edges` distinct grid edges and `loops`
+    coloured vertices drawn uniformly (a small rank at large n, so that all
+    solutions of a large grid can be traversed)."""
+    rng = np.random.default_rng(seed)
+    E = grid_edges(N)
+    A = np.zeros((N * N, N * N), dtype=np.uint8)
+    for k in rng.choice(len(E), size=edges, replace=False):
+        u, v = E[k]
+        A[u, v] = A[v, u] = 1
+    for v in rng.choice(N * N, size=loops, replace=False):
+        A[v, v] = 1
     return A
 
 

@@ -12,6 +12,8 @@
 //                           range (stage2.h); the block combines its waves in
 //                           LDS and adds to the outputs with one atomic each.
 //   reduce_general_kernel   W > 3: element by element.
+#include <type_traits>
+
 #include "hlf_device.h"
 #include "hlf_internal.h"
 #include "stage2.h"
@@ -281,15 +283,17 @@ __global__ __launch_bounds__(kTileThreads) void circuit_tile_kernel(
         if (tid == 0) *f.status = HLF_EINVAL;
         return;
     }
-    const uint64_t H = masks[0], Vm = masks[1], bb = masks[2];
-    const uint64_t l = f.shift[0];
-    uint64_t Rlo[V];
+    // The layers in the output width: n <= 32 bits fit one dword.
+    using U = typename std::conditional<sizeof(T) <= 4, uint32_t, uint64_t>::type;
+    const U H = (U)masks[0], Vm = (U)masks[1], bb = (U)masks[2];
+    const U l = (U)f.shift[0];
+    U Rlo[V];
 #pragma unroll
     for (int e = 0; e < V; ++e) {
         const uint64_t x = (uint64_t)(tid * V + e);
-        uint64_t R = 0;
+        U R = 0;
         for (int j = 0; j < S; ++j)
-            if ((x >> j) & 1ull) R ^= PM[j + 1] ^ PM[j];
+            if ((x >> j) & 1ull) R ^= (U)(PM[j + 1] ^ PM[j]);
         Rlo[e] = R;
     }
     const uint64_t end = begin + count;
@@ -298,17 +302,16 @@ __global__ __launch_bounds__(kTileThreads) void circuit_tile_kernel(
     if (t0 >= ntiles) return;
     const uint64_t t1 = (t0 + tiles_per_block < ntiles) ? t0 + tiles_per_block : ntiles;
     uint64_t Tt = (begin >> S) + t0;
-    uint64_t Rhi = 0;
+    U Rhi = 0;
     for (int j = 0; j + S < 64 && (Tt >> j); ++j)
-        if ((Tt >> j) & 1ull) Rhi ^= PM[S + j + 1] ^ PM[S + j];
+        if ((Tt >> j) & 1ull) Rhi ^= (U)(PM[S + j + 1] ^ PM[S + j]);
     for (uint64_t t = t0; t < t1; ++t, ++Tt) {
         uint64_t zv[V];
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-            const uint64_t R = Rlo[e] ^ Rhi;
-            const uint64_t y = ((R & H) << 1) ^ ((R >> 1) & H) ^ ((R & Vm) << N) ^
-                               ((R >> N) & Vm) ^ (R & bb);
-            zv[e] = y ^ l;
+            const U R = Rlo[e] ^ Rhi;
+            const U y = ((R & H) << 1) ^ ((R >> 1) & H) ^ ((R & Vm) << N) ^ ((R >> N) & Vm) ^ (R & bb);
+            zv[e] = (uint64_t)(U)(y ^ l);
         }
         const uint64_t i0 = (Tt << S) + (uint64_t)(tid * V);
         if (i0 >= begin && i0 + V <= end) {
@@ -328,7 +331,7 @@ __global__ __launch_bounds__(kTileThreads) void circuit_tile_kernel(
             }
         }
         const int c = S + __builtin_ctzll(Tt + 1) + 1;
-        Rhi ^= PM[c < 64 ? c : 64] ^ PM[S];
+        Rhi ^= (U)(PM[c < 64 ? c : 64] ^ PM[S]);
     }
 }
 
@@ -600,6 +603,157 @@ hlf_status launch_enumerate(const FactorIn &f, uint64_t begin, uint64_t count, i
     return launch_general<16, uint64_t>(f, begin, count, o, c, stream);
 }
 
+// ---------------------------------------------------------------------------
+// The paper's circuit for grids of more than 64 vertices (W > 1 words per
+// vector; the same layers as circuit_tile_kernel).  First one workgroup checks
+// that A is a subgraph of the N x N grid (every row's bits lie on the vertex
+// itself and its grid neighbours) and writes HLF_EINVAL otherwise, so the
+// materialising launch behind it on the stream writes nothing.  The
+// materialising kernel takes one lane per word, as enum_wide_tile_kernel:
+// thread (slot, w) holds word w of solutions base + slot + u*P, u < WMAX,
+// P = 1024 / WMAX.  R, the counter bits scattered onto the pivots, is linear
+// in the index: R = Rlo(slot + u*P) ^ Rhi(T) for a tile T of 1024 indices.
+// The edge layers shift R by 1 and by N bits across words; a lane takes the
+// neighbouring words of its solution from lanes w - 1 and w + 1.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void circuit_check_kernel(int32_t *status, const uint64_t *__restrict__ rows,
+                                                             int n, int W, int N) {
+    if (*(volatile int32_t *)status != HLF_OK) return;
+    int bad = 0;
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+        const int gr = v / N, gc = v - (v / N) * N;
+        for (int w = 0; w < W; ++w) {
+            uint64_t allowed = 0;
+            auto allow = [&](int u) {
+                if ((u >> 6) == w) allowed |= 1ull << (u & 63);
+            };
+            allow(v);
+            if (gc > 0) allow(v - 1);
+            if (gc < N - 1) allow(v + 1);
+            if (gr > 0) allow(v - N);
+            if (gr < N - 1) allow(v + N);
+            if (rows[(size_t)v * W + w] & ~allowed) bad = 1;
+        }
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) *status = HLF_EINVAL;
+}
+
+namespace {
+
+// x of lane - 1 / lane + 1 within the lane's 16-lane row (0 at the row edge).
+__device__ __forceinline__ uint64_t dpp_row_shr1(uint64_t x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, 0x111, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), 0x111, 0xf, 0xf, true);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ uint64_t dpp_row_shl1(uint64_t x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, 0x101, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), 0x101, 0xf, 0xf, true);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+template <int WMAX>
+__global__ __launch_bounds__(kTileThreads) void circuit_wide_kernel(
+    FactorIn f, const int32_t *__restrict__ pivots, const uint64_t *__restrict__ rows, int N,
+    uint64_t begin, uint64_t count, uint64_t *__restrict__ out, uint64_t tiles_per_block) {
+    constexpr int P = kTileThreads / WMAX;
+    constexpr int U = WMAX;
+    constexpr int S = kLogTileThreads;
+    constexpr int LOGP = S - (WMAX == 2 ? 1 : WMAX == 4 ? 2 : WMAX == 8 ? 3 : 4);
+    __shared__ uint64_t E[64 * WMAX];     // E[k][w] = word w of e_{p_k}, k < r
+    __shared__ uint64_t M[3 * WMAX];      // H, V (edge masks), b (colours)
+    int r;
+    if (!gate(f, begin, count, r)) return;
+    const int n = f.n, W = f.words;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < 64 * WMAX; idx += blockDim.x) {
+        const int k = idx / WMAX, w = idx - k * WMAX;
+        uint64_t e = 0;
+        if (k < r) {
+            const int p = pivots[k];
+            if ((p >> 6) == w) e = 1ull << (p & 63);
+        }
+        E[idx] = e;
+    }
+    // masks from three words per row: A[v][v+1], A[v][v+N], A[v][v]
+    {
+        const int v = tid;  // n <= 1024 = blockDim.x
+        bool h = false, vv = false, bb = false;
+        if (v < n) {
+            const int gr = v / N, gc = v - (v / N) * N;
+            const uint64_t *row = rows + (size_t)v * W;
+            if (gc < N - 1) h = (row[(v + 1) >> 6] >> ((v + 1) & 63)) & 1ull;
+            if (gr < N - 1) vv = (row[(v + N) >> 6] >> ((v + N) & 63)) & 1ull;
+            bb = (row[v >> 6] >> (v & 63)) & 1ull;
+        }
+        const uint64_t H = __ballot(h), V = __ballot(vv), B = __ballot(bb);
+        const int wave = tid >> 6;
+        if ((tid & 63) == 0 && wave < WMAX) {
+            M[wave] = H;
+            M[WMAX + wave] = V;
+            M[2 * WMAX + wave] = B;
+        }
+    }
+    __syncthreads();
+    const uint64_t end = begin + count;
+    const uint64_t ntiles = ((end - 1) >> S) - (begin >> S) + 1;
+    const uint64_t t0 = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * tiles_per_block;
+    if (t0 >= ntiles) return;
+    const uint64_t t1 = (t0 + tiles_per_block < ntiles) ? t0 + tiles_per_block : ntiles;
+    const int w = tid & (WMAX - 1);
+    const int slot = tid / WMAX;
+    const bool act = w < W;
+    const uint64_t Hw = M[w], Vw = M[WMAX + w], Bw = M[2 * WMAX + w];
+    const uint64_t Hm = w ? M[w - 1] : 0ull, Vm = w ? M[WMAX + w - 1] : 0ull;
+    const uint64_t lw = act ? f.shift[w] : 0ull;
+    // Rlo[u] = scatter of slot + u*P; bit j of slot is e_{p_j}, u*P adds LOGP + bits of u
+    uint64_t Rlo[U];
+    {
+        uint64_t x = 0;
+        for (int j = 0; j < LOGP; ++j)
+            if ((slot >> j) & 1) x ^= E[j * WMAX + w];
+        Rlo[0] = x;
+    }
+#pragma unroll
+    for (int u = 1; u < U; ++u) Rlo[u] = Rlo[u & (u - 1)] ^ E[(LOGP + __builtin_ctz(u)) * WMAX + w];
+    uint64_t Tt = (begin >> S) + t0;
+    uint64_t Rhi = 0;
+    for (int j = 0; j + S < 64 && (Tt >> j); ++j)
+        if ((Tt >> j) & 1ull) Rhi ^= E[(S + j) * WMAX + w];
+    const int Nr = 64 - N;
+    for (uint64_t t = t0; t < t1; ++t, ++Tt) {
+        const uint64_t base = Tt << S;
+        const bool full = base >= begin && base + (1u << S) <= end;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t R = Rlo[u] ^ Rhi;
+            // neighbouring words of the same solution (0 beyond the vector):
+            // DPP row shifts by one lane (a solution's WMAX lanes lie in one
+            // 16-lane row)
+            uint64_t Rd = dpp_row_shr1(R);
+            uint64_t Ru = dpp_row_shl1(R);
+            if (w == 0) Rd = 0;
+            if (w == WMAX - 1) Ru = 0;
+            const uint64_t X1 = R & Hw, X1d = Rd & Hm, X2 = R & Vw, X2d = Rd & Vm;
+            const uint64_t y = ((X1 << 1) | (X1d >> 63)) ^ (((R >> 1) | (Ru << 63)) & Hw) ^
+                               ((X2 << N) | (X2d >> Nr)) ^ (((R >> N) | (Ru << Nr)) & Vw) ^ (R & Bw);
+            const uint64_t z = y ^ lw;
+            const uint64_t i = base + (uint64_t)slot + (uint64_t)u * P;
+            if (act) {
+                if (full)
+                    __builtin_nontemporal_store(z, out + (i - begin) * W + w);
+                else if (i >= begin && i < end)
+                    out[(i - begin) * W + w] = z;
+            }
+        }
+        // next tile: the counter's carry flips bits S .. S + ctz(T + 1)
+        const int c = __builtin_ctzll(Tt + 1);
+        for (int j = 0; j <= c && S + j < 64; ++j) Rhi ^= E[(S + j) * WMAX + w];
+    }
+}
+
+}  // namespace
+
 hlf_status launch_circuit(const FactorIn &f, const int32_t *pivots, const uint64_t *rows, int N,
                           uint64_t begin, uint64_t count, int word_bits, void *out,
                           hipStream_t stream) {
@@ -616,7 +770,25 @@ hlf_status launch_circuit(const FactorIn &f, const int32_t *pivots, const uint64
     };
     if (word_bits == 16) return go(uint16_t{});
     if (word_bits == 32) return go(uint32_t{});
-    return go(uint64_t{});
+    if (word_bits == 64 && f.words == 1) return go(uint64_t{});
+    // W > 1 words per solution
+    const int W = f.words;
+    hipLaunchKernelGGL(circuit_check_kernel, dim3(1), dim3(1024), 0, stream, f.status, rows, f.n, W, N);
+    if (hipGetLastError() != hipSuccess) return HLF_EDEVICE;
+    auto wide = [&](auto wm) -> hlf_status {
+        constexpr int WMAX = decltype(wm)::value;
+        constexpr int S = kLogTileThreads;
+        const uint64_t ntiles = (end < begin) ? 1 : ((end - 1) >> S) - (begin >> S) + 1;
+        uint64_t blocks;
+        const uint64_t tpb = tiles_per_block_for(ntiles, (8ull * (uint64_t)W << S) / kWideRangeFactor, &blocks);
+        hipLaunchKernelGGL(circuit_wide_kernel<WMAX>, dim3((unsigned)blocks), dim3(kTileThreads), 0, stream,
+                           f, pivots, rows, N, begin, count, (uint64_t *)out, tpb);
+        return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;
+    };
+    if (W <= 2) return wide(std::integral_constant<int, 2>{});
+    if (W <= 4) return wide(std::integral_constant<int, 4>{});
+    if (W <= 8) return wide(std::integral_constant<int, 8>{});
+    return wide(std::integral_constant<int, 16>{});
 }
 
 hlf_status launch_reduce(const FactorIn &f, uint64_t begin, uint64_t count, bool accumulate,

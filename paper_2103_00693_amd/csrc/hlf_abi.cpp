@@ -138,12 +138,21 @@ hlf_status hlf_enumerate_circuit(const hlf_factors *f, const uint64_t *rows_dev,
                                  uint64_t begin, uint64_t count, int32_t word_bits, void *out_dev,
                                  hipStream_t stream) {
     if (!record_ok(f) || !rows_dev) return HLF_EINVAL;
-    if (f->words != 1 || grid_N < 1 || grid_N * grid_N != f->n) return HLF_EINVAL;
-    if ((word_bits != 16 && word_bits != 32 && word_bits != 64) || f->n > word_bits)
+    if (grid_N < 1 || grid_N * grid_N != f->n) return HLF_EINVAL;
+    if (f->words == 1) {
+        if ((word_bits != 16 && word_bits != 32 && word_bits != 64) || f->n > word_bits)
+            return HLF_EINVAL;
+    } else if (word_bits != 64 * f->words) {
         return HLF_EINVAL;
+    }
     if (count == 0) return HLF_OK;
-    const uint64_t V = 16 / (uint64_t)(word_bits / 8);
-    if (!out_dev || ((uintptr_t)out_dev & 15u) != 0 || begin % V != 0) return HLF_EINVAL;
+    if (!out_dev) return HLF_EINVAL;
+    if (f->words == 1) {
+        const uint64_t V = 16 / (uint64_t)(word_bits / 8);
+        if (((uintptr_t)out_dev & 15u) != 0 || begin % V != 0) return HLF_EINVAL;
+    } else if (((uintptr_t)out_dev & 7u) != 0) {
+        return HLF_EINVAL;
+    }
     return hlf::launch_circuit(view(f), f->pivots, rows_dev, grid_N, begin, count, word_bits,
                                out_dev, stream);
 }

@@ -292,9 +292,13 @@ def solve_dense(A: torch.Tensor, F: Factors, begin: int, count: int, word_bits: 
 
 def enumerate_circuit(F: Factors, rows: torch.Tensor, grid_N: int, begin: int, count: int,
                       word_bits: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """f1: hlf_enumerate_circuit -- the paper's circuit in binary-counter order."""
+    """f1: hlf_enumerate_circuit -- the paper's circuit in binary-counter order
+    (word_bits 16/32/64 for n <= 64, else 64*W: out is int64 (count, W))."""
     if out is None:
-        out = torch.empty(count, dtype=_DTYPES[word_bits], device=F.device)
+        if word_bits in _DTYPES and F.n <= word_bits:
+            out = torch.empty(count, dtype=_DTYPES[word_bits], device=F.device)
+        else:
+            out = torch.empty((count, word_bits // 64), dtype=torch.int64, device=F.device)
     _check(lib().hlf_enumerate_circuit(F.c, _ptr(rows), grid_N, begin, count, word_bits,
                                        _ptr(out) if count else None, _stream(stream)),
            "hlf_enumerate_circuit")

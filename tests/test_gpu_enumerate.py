@@ -10,12 +10,12 @@ import numpy as np
 import pytest
 import torch
 
-from hlf_inputs import CONFIG2_SEEDS, grid_instance, random_symmetric
+from hlf_inputs import CONFIG2_SEEDS, grid_instance, random_symmetric, sparse_grid_instance
 from oracle import c_oracle as C
 from oracle import hlf_oracle as O
 from paper_2103_00693_amd import hlf
 
-from gpu_util import gpu_factor, narrow_to_u64, require_gpu
+from gpu_util import gpu_factor, narrow_to_u64, require_gpu, words_to_ints
 
 pytestmark = pytest.mark.gpu
 
@@ -297,3 +297,47 @@ def test_circuit_rejects_non_grid_and_bad_arguments():
         hlf.enumerate_circuit(G, gpu_rows(grid_instance(3, seed=1)), 4, 0, 16, 16)  # N^2 != n
     with pytest.raises(hlf.HlfError):
         hlf.enumerate_circuit(G, gpu_rows(grid_instance(3, seed=1)), 3, 3, 16, 16)  # begin % 8
+
+
+@pytest.mark.parametrize("N,edges,loops,seed", [(9, 12, 3, 1), (10, 10, 5, 2), (16, 14, 4, 3),
+                                                (23, 16, 2, 4), (32, 12, 6, 5)])
+def test_circuit_multiword_grids(N, edges, loops, seed):
+    """n > 64 (W = 2..16 words): the circuit's layers as multi-word shifts,
+    every word against the C oracle's counter order (itself pinned to the
+    layer-by-layer circuit), for full tiles and ragged ranges."""
+    A = sparse_grid_instance(N, edges, seed, loops)
+    Fo = O.factor(A)
+    r, W = Fo["rank"], Fo["words"]
+    F, st = gpu_factor(A)
+    assert st == hlf.HLF_OK and 1 <= r <= 40
+    rows = gpu_rows(A)
+    total = 1 << r
+    ranges = [(0, min(total, 5000)), (3, min(total - 3, 1 << 14)), (max(0, total - 1029), min(total, 1029))]
+    if total > (1 << 16):
+        ranges.append((total // 2 + 7, 70000))
+    for begin, count in ranges:
+        print(f"[circuit] multiword N={N} W={W} r={r} begin={begin} count={count}", flush=True)
+        out = hlf.enumerate_circuit(F, rows, N, begin, count, 64 * W)
+        torch.cuda.synchronize()
+        assert int(F.status.item()) == hlf.HLF_OK
+        assert np.array_equal(hlf.as_uint64(out).reshape(count, W), C.enumerate_counter_range(Fo, begin, count))
+    # the literal Python circuit (vertex by vertex, O(n^2) per index) on the first indices
+    k = 64 if N * N <= 256 else 4
+    out = hlf.enumerate_circuit(F, rows, N, 0, k, 64 * W)
+    torch.cuda.synchronize()
+    assert words_to_ints(hlf.as_uint64(out).reshape(k, W)) == O.enumerate_counter_order(A, Fo, 0, k)
+
+
+def test_circuit_multiword_rejects_non_grid():
+    A = sparse_grid_instance(12, 10, 9)
+    A[0, 40] = A[40, 0] = 1  # not a grid edge
+    F, st = gpu_factor(A)
+    assert st == hlf.HLF_OK
+    out = torch.full((256, 3), -4, dtype=torch.int64, device="cuda")
+    hlf.enumerate_circuit(F, gpu_rows(A), 12, 0, 256, 192, out=out)
+    torch.cuda.synchronize()
+    assert int(F.status.item()) == hlf.HLF_EINVAL
+    assert bool((out == -4).all())
+    G, _ = gpu_factor(sparse_grid_instance(12, 10, 8))
+    with pytest.raises(hlf.HlfError):
+        hlf.enumerate_circuit(G, gpu_rows(sparse_grid_instance(12, 10, 8)), 12, 0, 16, 64)  # word_bits != 64*W
