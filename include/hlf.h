@@ -203,10 +203,12 @@ hlf_status hlf_enumerate_ex(const hlf_factors *f, uint64_t begin, uint64_t count
  * y XOR l (the final CNOT layer).  Equivalently z = l XOR (XOR over set bits
  * k of i of B_k): the same solution set as hlf_enumerate in another order.
  *   rows_dev  packed A (as for hlf_factor); A must be a subgraph of the
- *             grid_N x grid_N grid, n = grid_N^2 <= 64, vertices row-major
- *             (else HLF_EINVAL in f->status, nothing written).
- *   word_bits 16/32/64 with n <= word_bits; begin a multiple of
- *             16/(word_bits/8) and a 16-byte aligned out_dev (else HLF_EINVAL).
+ *             grid_N x grid_N grid, n = grid_N^2 <= HLF_MAX_N, vertices
+ *             row-major (else HLF_EINVAL in f->status, nothing written).
+ *   word_bits n <= 64: 16/32/64 with n <= word_bits, begin a multiple of
+ *             16/(word_bits/8) and a 16-byte aligned out_dev; n > 64: 64*W
+ *             (W uint64 words per solution, 8-byte aligned out_dev).  Else
+ *             HLF_EINVAL.
  * Device errors as hlf_enumerate.                                               */
 hlf_status hlf_enumerate_circuit(const hlf_factors *f, const uint64_t *rows_dev, int32_t grid_N,
                                  uint64_t begin, uint64_t count, int32_t word_bits, void *out_dev,
