@@ -50,8 +50,8 @@ REDUCE_VALU_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_a
 # dispatch), each scaled by what the same counter reads for a plain 256 MiB
 # device copy (WRITE_SIZE 262144 KiB -> x1.0, FETCH_SIZE 131085 KiB -> x2.0).
 # Valid only for the kernel sources it was taken on (sha256 prefix below).
-ENUM_TRAFFIC = {"src_sha256_16": "2b117e86797210cf", "fetch_kib_raw": 69.5, "fetch_scale": 2.0,
-                "write_kib_raw": 688687.6, "write_scale": 1.0}
+ENUM_TRAFFIC = {"src_sha256_16": "22ef894c3eb80077", "fetch_kib_raw": 69.2, "fetch_scale": 2.0,
+                "write_kib_raw": 688822.9, "write_scale": 1.0}
 ENUM_TRAFFIC_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/batch.hip",
                         "paper_2103_00693_amd/csrc/factor_wave.h",
                         "paper_2103_00693_amd/csrc/hlf_device.h")
