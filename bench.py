@@ -42,7 +42,7 @@ REDUCE_VALU_OPS_PER_SOLUTION = 17
 # 10,200,547,328 solutions = 19.02 lane operations per solution (the full-tile
 # loop plus per-tile and per-wave work).  The roofline uses it while the
 # kernel's sources are the measured ones, else the loop count above.
-REDUCE_VALU_MEASURED = {"src_sha256_16": "cbd8450aca25468c", "ops_per_solution": 19.02}
+REDUCE_VALU_MEASURED = {"src_sha256_16": "322899540ce79507", "ops_per_solution": 19.02}
 REDUCE_VALU_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/enumerate.hip",
                        "paper_2103_00693_amd/csrc/hlf_device.h")
 # HBM traffic of one batch_enum_kernel<uint32_t, overlap> launch of the headline step,
