@@ -8,6 +8,8 @@
 // workgroup; each thread produces whole samples, reading every basis row at a
 // wave-uniform address (an LDS broadcast) and applying it under a mask, so no
 // lane diverges.  Larger n run on the matrix cores (below).
+#include <type_traits>
+
 #include "hlf_device.h"
 #include "hlf_internal.h"
 
@@ -104,6 +106,63 @@ constexpr int kMfmaMaxKC = HLF_MAX_N / 64;
 constexpr int kE2M1 = 4;         // operand format code of the instruction
 constexpr int kScaleOne = 127;   // E8M0 scale 2^0
 constexpr float kTwo23 = 8388608.0f;
+// Blocks one wave takes at most in one launch: 2^23 + 4096 * HLF_MAX_N < 2^24.
+constexpr int kMaxWaveBlocks = 4096;
+
+// 32x32 bit transposes within each half of the wave, on the VALU alone:
+// lane l of a half holds row l of each matrix and gets its column l.  Step j
+// exchanges, between lanes l and l ^ j, the bits whose row and column indices
+// differ in bit j (the lane with bit j clear keeps the columns with bit j
+// clear and takes its partner's, moved up by j; the other keeps the columns
+// with bit j set and takes its partner's, moved down).  Partners: j = 16 by
+// a permlane16 swap of the two rows of 16, j = 8 by a row mirror then a half
+// mirror, j = 4 by a half mirror then a quad mirror, j = 2 and 1 by quad
+// permutations (DPP).  Byte and halfword steps merge with one byte permute,
+// the others with a masked rotate and an and-or.
+template <int N>
+__device__ __forceinline__ void half_transpose32_n(uint32_t (&x)[N]) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    {   // j = 16
+        const bool up = lane & 16;
+        const uint32_t sel = up ? 0x03020706u : 0x05040100u;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const auto sw = __builtin_amdgcn_permlane16_swap(x[i], x[i], false, false);
+            const uint32_t y = up ? sw[0] : sw[1];
+            x[i] = __builtin_amdgcn_perm(y, x[i], sel);
+        }
+    }
+    {   // j = 8
+        const uint32_t sel = (lane & 8) ? 0x03070105u : 0x06020400u;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int t = __builtin_amdgcn_update_dpp(0, (int)x[i], 0x140, 0xF, 0xF, false);   // row mirror
+            const uint32_t y = (uint32_t)__builtin_amdgcn_update_dpp(0, t, 0x141, 0xF, 0xF, false);  // half mirror
+            x[i] = __builtin_amdgcn_perm(y, x[i], sel);
+        }
+    }
+#pragma unroll
+    for (int step = 2; step >= 0; --step) {
+        const int j = 1 << step;
+        const uint32_t mj = j == 4 ? 0x0F0F0F0Fu : j == 2 ? 0x33333333u : 0x55555555u;
+        const uint32_t M = (lane & j) ? ~mj : mj;
+        const uint32_t R = (lane & j) ? (uint32_t)j : (uint32_t)(32 - j);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            int y;
+            if (j == 4) {
+                const int t = __builtin_amdgcn_update_dpp(0, (int)x[i], 0x141, 0xF, 0xF, false);  // half mirror
+                y = __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, false);                     // quad [3,2,1,0]
+            } else if (j == 2) {
+                y = __builtin_amdgcn_update_dpp(0, (int)x[i], 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
+            } else {
+                y = __builtin_amdgcn_update_dpp(0, (int)x[i], 0xB1, 0xF, 0xF, false);  // quad [1,0,3,2]
+            }
+            const uint32_t t = (uint32_t)y & M;
+            x[i] = (x[i] & M) | __builtin_amdgcn_alignbit(t, t, R);
+        }
+    }
+}
 
 // JC column chunks (JC/2 words of every sample) per workgroup, WAVES waves.
 template <int JC, int WAVES>
@@ -121,17 +180,18 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
     const int w0 = QW * (int)blockIdx.x;
     const int nq = min(QW, W - w0);   // words of this group that exist
     // B operands.  A wave takes one (kc, word q) tile: lane t loads the word
-    // of B_{64kc+t}; after the 64x64 transpose lane b holds bit 64q + b of
-    // every row of the tile (bit t <-> k = 64kc + t).  One permlane32 swap of
-    // the halves then gives lane (h, m) half h of column 64q + m (chunk 2q,
-    // first) and of column 64q + 32 + m (chunk 2q + 1, second).  Nibble t of
-    // dword d holds k = 32h + 4t + d at position 2, 1, 0, 0 for d = 0..3.
+    // of B_{64kc+t}.  Lanes 32h .. 32h+31 then hold rows 64kc + 32h + 0..31;
+    // their low dwords (columns 64q + 0..31) and high dwords (64q + 32..63),
+    // each transposed within the half, give lane (h, m) half h of column
+    // 64q + m (chunk 2q, first) and of column 64q + 32 + m (chunk 2q + 1,
+    // second).  Nibble t of dword d holds k = 32h + 4t + d at position 2, 1,
+    // 0, 0 for d = 0..3.
     for (int t = wave; t < KC * QW; t += WAVES) {
         const int kc = t / QW, q = t - kc * QW;
         const int k = 64 * kc + lane;
         const uint64_t x = (k < r && q < nq) ? f.basis[(size_t)k * W + w0 + q] : 0ull;
-        const uint64_t xt = wave_transpose64(x);
-        const auto y2 = __builtin_amdgcn_permlane32_swap((uint32_t)xt, (uint32_t)(xt >> 32), false, false);
+        uint32_t y2[2] = {(uint32_t)x, (uint32_t)(x >> 32)};
+        half_transpose32_n<2>(y2);
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const uint32_t y = y2[e];
@@ -154,10 +214,21 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
     const uint64_t nblk = (num + 31) >> 5;
     const uint64_t per_wg = (nblk + gridDim.y - 1) / gridDim.y;
     const uint64_t blk_end = min(nblk, (uint64_t)(blockIdx.y + 1) * per_wg);
-    for (uint64_t blk = (uint64_t)blockIdx.y * per_wg + wave; blk < blk_end; blk += WAVES) {
+    // A wave's sums run on from one of its blocks to the next: only its first
+    // block starts from 2^23, later ones add their first K chunk to the
+    // previous block's sums.  A sum is then 2^23 plus the counts of all the
+    // wave's blocks so far (below 2^24: the launch gives a wave at most
+    // kMaxWaveBlocks blocks, of counts <= r <= HLF_MAX_N), its bit 0 the
+    // parity of that total, and a block's output bits are the XOR of its
+    // parity word and the previous one.
+    v16f acc[JC];
+    uint64_t prev[QW];
+#pragma unroll
+    for (int q = 0; q < QW; ++q) prev[q] = 0ull;
+    auto block = [&](uint64_t blk, auto seeded) {
+        constexpr bool kSeeded = decltype(seeded)::value;
         const uint64_t s = 32ull * blk + (uint64_t)m;  // this lane's A row
         const bool live = s < num;
-        v16f acc[JC];
         // Coefficient words 2p, 2p+1 of this row are K chunks 2p, 2p+1: lane
         // half h generates word 2p+h (SplitMix64 state seed + (ctr+1) gamma,
         // advanced by 2 gamma per step).  One swap of the upper 32 lanes of
@@ -183,12 +254,14 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
                 const v4i b4 = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * JC + jc) * 64 + lane) * 4]);
                 const v8i b = {b4[0], b4[1], b4[2], b4[3], 0, 0, 0, 0};
                 acc[jc] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                    b, a, first ? magic : acc[jc], kE2M1, kE2M1, 0, kScaleOne, 0, kScaleOne);
+                    b, a, (first && kSeeded) ? magic : acc[jc], kE2M1, kE2M1, 0, kScaleOne, 0, kScaleOne);
             }
         };
         if (KC == 0) {
+            if constexpr (kSeeded) {
 #pragma unroll
-            for (int jc = 0; jc < JC; ++jc) acc[jc] = magic;
+                for (int jc = 0; jc < JC; ++jc) acc[jc] = magic;
+            }
         } else {
             auto ys = words(0);
             chunk(0, ys[0], true);
@@ -220,12 +293,17 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
             word[jc] = mine | __builtin_amdgcn_permlane32_swap(mine, mine, false, false)[1];
         }
         const uint64_t so = 32ull * blk + (uint64_t)lane;  // row `lane` for lanes < 32
-        if (lane < 32 && so < num) {
 #pragma unroll
-            for (int q = 0; q < QW; ++q)
-                if (q < nq)
-                    out[so * W + w0 + q] = (((uint64_t)word[2 * q + 1] << 32) | word[2 * q]) ^ l[q];
+        for (int q = 0; q < QW; ++q) {
+            const uint64_t z = ((uint64_t)word[2 * q + 1] << 32) | word[2 * q];
+            if (lane < 32 && so < num && q < nq) out[so * W + w0 + q] = z ^ prev[q] ^ l[q];
+            prev[q] = z;
         }
+    };
+    uint64_t blk = (uint64_t)blockIdx.y * per_wg + wave;
+    if (blk < blk_end) {
+        block(blk, std::true_type{});
+        for (blk += WAVES; blk < blk_end; blk += WAVES) block(blk, std::false_type{});
     }
 }
 
@@ -241,6 +319,10 @@ hlf_status launch_sample_mfma_t(const FactorIn &f, uint64_t seed, uint64_t num,
     const uint64_t most = (blocks32 + WAVES - 1) / WAVES;
     if (y > most) y = most;
     if (y == 0) y = 1;
+    // at most kMaxWaveBlocks blocks per wave (the running sums stay exact)
+    const uint64_t least = (blocks32 + (uint64_t)kMaxWaveBlocks * WAVES - 1) / ((uint64_t)kMaxWaveBlocks * WAVES);
+    if (y < least) y = least;
+    if (y > 0xFFFFull) return HLF_EINVAL;
     hipLaunchKernelGGL((sample_mfma_kernel<JC, WAVES>), dim3(groups, (unsigned)y),
                        dim3(64 * WAVES), 0, stream, f, seed, num, coeffs, out);
     return hipGetLastError() == hipSuccess ? HLF_OK : HLF_EDEVICE;

@@ -90,6 +90,46 @@ def test_sample_65536_n1024_every_word(name):
     assert np.array_equal(hlf.as_uint64(out), want)
 
 
+def test_sample_long_runs_of_blocks():
+    """2^22 samples, so that every wave of the matrix-core kernel chains its
+    sums over many 32-sample blocks (about 85 at n = 289, 170 at n = 1024):
+    every word at n = 289 for the SplitMix64 stream, and 4096 rows spread
+    over the range at n = 1024 for explicit coefficients, against the C
+    oracle."""
+    num = 1 << 22
+    A = grid_instance(17, p=0.5, seed=4)
+    Fo = O.factor(A)
+    F, st = gpu_factor(A)
+    W = Fo["words"]
+    assert st == hlf.HLF_OK and int(F.rank.item()) == Fo["rank"]
+    _say(f"[full] sample n=289 r={Fo['rank']} num={num}")
+    out = hlf.sample(F, 0xC0FFEE, num)
+    torch.cuda.synchronize()
+    got = hlf.as_uint64(out).reshape(num, W)
+    want = C.sample(Fo, 0xC0FFEE, num)
+    bad = np.nonzero((got != want).any(axis=1))[0]
+    assert bad.size == 0, f"{bad.size} samples differ, first {bad[:8].tolist()}"
+    del out, got, want
+
+    A = random_symmetric(1024, 8, 0.5)
+    Fo = O.factor(A)
+    F, st = gpu_factor(A)
+    r = Fo["rank"]
+    R64 = (r + 63) // 64
+    rng = np.random.default_rng(29)
+    coeffs = rng.integers(-(2**63), 2**63 - 1, size=(num, R64), dtype=np.int64)
+    _say(f"[full] sample n=1024 r={r} explicit coefficients num={num}")
+    out = torch.empty((num, 16), dtype=torch.int64, device="cuda")
+    out.fill_(-1)
+    hlf.sample(F, 0, num, coeffs=torch.from_numpy(coeffs).cuda(), out=out)
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([np.arange(0, num, 1024), rng.integers(0, num, 2048), np.arange(num - 64, num)]))
+    got = hlf.as_uint64(out)[rows]
+    want = C.sample(Fo, 0, rows.size, coeffs=coeffs[rows].view(np.uint64))
+    bad = np.nonzero((got != want).any(axis=1))[0]
+    assert bad.size == 0, f"{bad.size} of {rows.size} rows differ, first rows {rows[bad[:8]].tolist()}"
+
+
 def _mixed_strings(Fo, n, num, seed):
     """num strings: a quarter exact samples, a quarter samples with one
     flipped bit, a quarter with two (possibly equal) flipped bits, the rest
