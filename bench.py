@@ -45,6 +45,14 @@ REDUCE_VALU_OPS_PER_SOLUTION = 17
 REDUCE_VALU_MEASURED = {"src_sha256_16": "322899540ce79507", "ops_per_solution": 19.02}
 REDUCE_VALU_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/enumerate.hip",
                        "paper_2103_00693_amd/csrc/hlf_device.h")
+# Measured: rocprofv3 --pmc SQ_INSTS_VALU over the five timed sample launches of
+# the sample mode (65536 samples of the N=32 grid, p=0.5, seed 17; the basis
+# has at most 5 set bits per row and column, so every workgroup takes the
+# sparse path): 4,585,984 wave instructions x 64 lanes / 65536 samples =
+# 4478.5 lane operations per sample.  Used while the sampler's sources are
+# the measured ones.
+SAMPLE_VALU_MEASURED = {"src_sha256_16": "87f26b4db7b0a753", "ops_per_sample": 4478.5}
+SAMPLE_VALU_SOURCES = ("paper_2103_00693_amd/csrc/sample.hip", "paper_2103_00693_amd/csrc/hlf_device.h")
 # HBM traffic of one batch_enum_kernel<uint32_t, overlap> launch of the headline step,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch), each scaled by what the same counter reads for a plain 256 MiB
@@ -93,6 +101,15 @@ def reduce_valu_ops_per_solution():
     if _sources_sha256_16(REDUCE_VALU_SOURCES) == REDUCE_VALU_MEASURED["src_sha256_16"]:
         return REDUCE_VALU_MEASURED["ops_per_solution"], "SQ_INSTS_VALU x 64 / solutions (rocprofv3)"
     return REDUCE_VALU_OPS_PER_SOLUTION, "full-tile loop instruction count (assembly)"
+
+
+def sample_valu_ops_per_sample():
+    """VALU lane operations per sample of the sample mode's workload (sparse
+    path), or None if the sampler's sources changed since the counters were
+    taken."""
+    if _sources_sha256_16(SAMPLE_VALU_SOURCES) == SAMPLE_VALU_MEASURED["src_sha256_16"]:
+        return SAMPLE_VALU_MEASURED["ops_per_sample"]
+    return None
 
 
 def enum_traffic_bytes():
@@ -284,6 +301,12 @@ def general_mode(hlf, torch, stream, dev):
         "factor_ms": round(_timed(torch, stream, lambda: hlf.factor(rows, 1024, F, stream=stream), 5) * 1e3, 4),
         "ms_per_65536_samples": round(_timed(torch, stream, lambda: hlf.sample(F, 3, 65536, out=smp, stream=stream), 5) * 1e3, 4),
     }
+    # dense basis (up to hundreds of set bits per row): the matrix-core path
+    rk = out["dense"]["rank"]
+    fl = 2.0 * 65536 * rk * 1024 / (out["dense"]["ms_per_65536_samples"] * 1e-3) / 1e12
+    out["dense"]["sample_roofline"] = {"bound": "mfma", "kernel": "sample_mfma_kernel (fp4 E2M1 32x32x64, fp32 sums)",
+                                       "achieved": round(fl, 1), "peak": FP4_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                       "frac": round(fl / FP4_MFMA_PEAK_TFLOPS, 4)}
     del smp
     A = torch.from_numpy(low_rank_symmetric(1024, 24, seed=2)).to(dev)
     hlf.pack_dense(A, rows, st, stream=stream)
@@ -797,14 +820,36 @@ def main():
             stream.synchronize()
             fac_s = e0.elapsed_time(e1) * 1e-3 / reps
             rk = int(F.rank.item())
-            ops = 2.0 * 65536 * rk * 1024 / smp_s / 1e12  # multiply-adds of the GF(2) product, x2
+            # Basis weights per 256-column group (the sampler's unit for
+            # choosing between its sparse path and the matrix cores).
+            bw = np.ascontiguousarray(F.basis.cpu().numpy()[:rk]).view(np.uint64)  # [r, 16]
+            bits = np.unpackbits(bw.view(np.uint8), axis=1, bitorder="little")  # [r, 1024]
+            grp = [bits[:, 256 * g:256 * (g + 1)] for g in range(4)]
+            max_row = max(int(b.sum(axis=1).max(initial=0)) for b in grp)
+            max_col = max(int(b.sum(axis=0).max(initial=0)) for b in grp)
+            sparse = max_row <= 16 and max_col <= 16
+            dense_ops = 2.0 * 65536 * rk * 1024 / smp_s / 1e12  # the dense GF(2) product's multiply-adds, x2
+            per = sample_valu_ops_per_sample()
+            if sparse:
+                roof = {"bound": "alu", "kernel": "sample_mfma_kernel, sparse path (bit slices, row lists gathered in LDS)",
+                        "achieved": round(per * 65536 / smp_s / 1e12, 2) if per else None,
+                        "peak": round(VALU_PEAK_TOPS, 2), "unit": "T VALU instr-lane-ops/s",
+                        "frac": round(per * 65536 / smp_s / 1e12 / VALU_PEAK_TOPS, 4) if per else None,
+                        "valu_ops_per_sample": per,
+                        "valu_ops_source": "SQ_INSTS_VALU x 64 / samples (rocprofv3)" if per else "sources changed since the counters were taken"}
+            else:
+                roof = {"bound": "mfma", "kernel": "sample_mfma_kernel (fp4 E2M1 32x32x64, fp32 sums)",
+                        "achieved": round(dense_ops, 1), "peak": FP4_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(dense_ops / FP4_MFMA_PEAK_TFLOPS, 4), "ops_per_sample": 2 * rk * 1024}
             return {"workload": "N=32 grid (n=1024), p=0.5: 65536 uniform samples",
                     "rank": rk, "samples_per_s": round(65536 / smp_s, 1),
                     "ms_per_65536": round(smp_s * 1e3, 4),
-                    "roofline": {"bound": "mfma", "kernel": "sample_mfma_kernel (fp4 E2M1 32x32x64, fp32 sums)",
-                                 "achieved": round(ops, 1), "peak": FP4_MFMA_PEAK_TFLOPS,
-                                 "unit": "TFLOP/s", "frac": round(ops / FP4_MFMA_PEAK_TFLOPS, 4),
-                                 "ops_per_sample": 2 * rk * 1024},
+                    "path": "sparse" if sparse else "matrix cores",
+                    "basis_max_row_weight": max_row, "basis_max_col_weight": max_col,
+                    "roofline": roof,
+                    "dense_product_equivalent": {"TFLOP_s": round(dense_ops, 1),
+                                                 "frac_of_fp4_peak": round(dense_ops / FP4_MFMA_PEAK_TFLOPS, 4),
+                                                 "note": "rate of the dense fp4 product that gives the same samples"},
                     "factor_ms_n1024": round(fac_s * 1e3, 4)}
 
         only = set(x for x in args.only.split(",") if x)

@@ -164,33 +164,244 @@ __device__ __forceinline__ void half_transpose32_n(uint32_t (&x)[N]) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Sparse bases.  B_k is column p_k of A, so on the paper's 2D grids every
+// basis row and every basis column has at most five set bits (a vertex and
+// its neighbours), and sampling is a sparse product: bit j of z_s is l_j XOR
+// the coefficient bits c_{s,k} of the rows k with B_k[j] = 1.  A workgroup
+// whose rows and columns have at most kSparseMaxW set bits in its columns
+// takes this path instead of the matrix cores.  Per 32-sample block, the
+// coefficient words of the K chunks that touch its columns are transposed
+// into bit slices (slice k holds c_{s,k} of the block's 32 samples, one bit
+// per sample) in a per-wave LDS table; each output column XORs the slices of
+// the rows in its list, and the output slices are transposed back into the
+// samples' words.
+// ---------------------------------------------------------------------------
+constexpr int kSparseMaxW = 16;  // set bits per basis row and column (in the group) at most
+
+// LDS layout of the sparse path, in dwords from the start of the workgroup's
+// buffer (it aliases the matrix-core operands, which are not built then).
+// RMAX bounds the rows (64 ceil(n/64)); NCOL = 64 * words per group.
+constexpr int kSpRowCnt = 0;                      // [RMAX] row weights
+constexpr int kSpMaxW = kSpRowCnt + HLF_MAX_N;    // largest row weight
+constexpr int kSpPairs = kSpMaxW + 1;             // K-chunk pairs with any set bit (mask)
+constexpr int kSpMaxC = kSpPairs + 1;             // largest column weight
+constexpr int kSpColCnt = kSpMaxC + 1;            // [NCOL] column weights
+constexpr int kSpLists = (kSpColCnt + 256 + 3) / 4 * 4;  // [NCOL][kSparseMaxW] u16 row lists (16-byte aligned)
+constexpr int kSpSlices = kSpLists + 256 * kSparseMaxW / 2;  // per wave: [RMAX + 4] slices
+static_assert(kSpLists % 4 == 0 && kSpSlices % 4 == 0, "16-byte aligned lists");
+
+// Slices per wave: every k the K-chunk pairs reach, 64 * 2 * ceil(KC/2)
+// (the JC = 4 kernel serves W <= 3, so KC <= 3), then a zero slice.
+template <int JC>
+constexpr int sparse_rmax() { return JC == 4 ? 256 : HLF_MAX_N; }
+
+// The 32-sample blocks of the sparse path.
+template <int JC, int WAVES, int MWB>
+__device__ __forceinline__ void sample_sparse_blocks(const FactorIn &f, int r, uint64_t seed, uint64_t num,
+                                                     const uint64_t *__restrict__ coeffs,
+                                                     uint64_t *__restrict__ out, uint32_t *lds) {
+    constexpr int QW = JC / 2;
+    constexpr int RMAX = sparse_rmax<JC>();
+    const int W = f.words;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, m = lane & 31;
+    const int KC = (r + 63) >> 6;
+    const int w0 = QW * (int)blockIdx.x;
+    const int nq = min(QW, W - w0);
+    const uint32_t pairs = lds[kSpPairs];
+    const uint16_t *lists = reinterpret_cast<const uint16_t *>(lds + kSpLists);
+    uint32_t *cs = lds + kSpSlices + wave * (RMAX + 4);  // cs[RMAX] stays zero
+    // Lane (h, m) gathers the output columns 64c + 32h + m: their row lists
+    // (unused entries hold RMAX, the index of a zero slice) and bits of l.
+    uint32_t lbit[QW];
+#pragma unroll
+    for (int c = 0; c < QW; ++c) {
+        const uint32_t lw = c < nq ? reinterpret_cast<const uint32_t *>(f.shift)[2 * (w0 + c) + h] : 0u;
+        lbit[c] = 0u - ((lw >> m) & 1u);
+    }
+    uint32_t *out32 = reinterpret_cast<uint32_t *>(out);
+    const uint64_t nblk = (num + 31) >> 5;
+    const uint64_t per_wg = (nblk + gridDim.y - 1) / gridDim.y;
+    const uint64_t blk_end = min(nblk, (uint64_t)(blockIdx.y + 1) * per_wg);
+    for (uint64_t blk = (uint64_t)blockIdx.y * per_wg + wave; blk < blk_end; blk += WAVES) {
+        const uint64_t s = 32ull * blk + (uint64_t)m;  // lane (h, m): sample m of the block
+        const bool live = s < num;
+        for (int p = 0; 2 * p < KC; ++p) {
+            if (!((pairs >> p) & 1u)) continue;  // wave-uniform
+            // Lane half h makes coefficient word 2p + h of its sample; within
+            // each half, the low and high dwords transposed give lane (h, m)
+            // the slices of k = 64(2p+h) + m and 64(2p+h) + 32 + m.
+            const int kc = 2 * p + h;
+            const bool use = live && kc < KC;
+            const uint64_t ctr = s * (uint64_t)KC + (uint64_t)kc;
+            uint64_t word;
+            if (coeffs) {  // wave-uniform
+                word = use ? coeffs[ctr] : 0ull;
+            } else {
+                word = mix13(seed + (ctr + 1) * kGamma) & (0ull - (uint64_t)use);
+            }
+            uint32_t y[2] = {(uint32_t)word, (uint32_t)(word >> 32)};
+            half_transpose32_n<2>(y);
+            cs[64 * kc + m] = y[0];
+            cs[64 * kc + 32 + m] = y[1];
+        }
+        // All list entries first, then all slice reads in flight together,
+        // then the XORs.
+        uint32_t kk[QW][MWB / 2];
+#pragma unroll
+        for (int c = 0; c < QW; ++c) {
+            const uint4 *lp = reinterpret_cast<const uint4 *>(lists + (64 * c + 32 * h + m) * kSparseMaxW);
+#pragma unroll
+            for (int g = 0; g < MWB / 8; ++g) {
+                const uint4 q4 = lp[g];
+                kk[c][4 * g] = q4.x;
+                kk[c][4 * g + 1] = q4.y;
+                kk[c][4 * g + 2] = q4.z;
+                kk[c][4 * g + 3] = q4.w;
+            }
+        }
+        uint32_t sv[QW][MWB];
+#pragma unroll
+        for (int c = 0; c < QW; ++c)
+#pragma unroll
+            for (int i = 0; i < MWB; ++i) sv[c][i] = cs[(kk[c][i >> 1] >> (16 * (i & 1))) & 0xFFFFu];
+        uint32_t v[QW];
+#pragma unroll
+        for (int c = 0; c < QW; ++c) {
+            uint32_t acc = lbit[c];
+#pragma unroll
+            for (int i = 0; i < MWB; ++i) acc ^= sv[c][i];
+            v[c] = acc;
+        }
+        // Slice of column 64c + 32h + m, transposed within the half: lane
+        // (h, m) gets dword h of word c of sample m.
+        half_transpose32_n<QW>(v);
+#pragma unroll
+        for (int c = 0; c < QW; ++c)
+            if (live && c < nq) out32[(s * (uint64_t)W + (uint64_t)(w0 + c)) * 2 + h] = v[c];
+    }
+}
+
 // JC column chunks (JC/2 words of every sample) per workgroup, WAVES waves.
 template <int JC, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
     FactorIn f, uint64_t seed, uint64_t num, const uint64_t *__restrict__ coeffs,
     uint64_t *__restrict__ out) {
     constexpr int QW = JC / 2;  // words per workgroup
+    constexpr int TPW = (kMfmaMaxKC * QW + WAVES - 1) / WAVES;  // basis tiles per wave, at most
     __shared__ __align__(16) uint32_t Bop[kMfmaMaxKC * JC * 64 * 4];
-    if (*(volatile int32_t *)f.status != HLF_OK) return;
-    const int r = *f.rank;
+    static_assert(kSpSlices + WAVES * (sparse_rmax<JC>() + 4) <= kMfmaMaxKC * JC * 64 * 4, "sparse layout fits");
+    static_assert(64 * QW <= 256 && 64 * QW <= 64 * WAVES, "one column per thread");
     const int W = f.words;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, m = lane & 31;
-    const int KC = (r + 63) >> 6;     // K chunks of 64 = coefficient words
     const int w0 = QW * (int)blockIdx.x;
     const int nq = min(QW, W - w0);   // words of this group that exist
-    // B operands.  A wave takes one (kc, word q) tile: lane t loads the word
-    // of B_{64kc+t}.  Lanes 32h .. 32h+31 then hold rows 64kc + 32h + 0..31;
-    // their low dwords (columns 64q + 0..31) and high dwords (64q + 32..63),
-    // each transposed within the half, give lane (h, m) half h of column
-    // 64q + m (chunk 2q, first) and of column 64q + 32 + m (chunk 2q + 1,
-    // second).  Nibble t of dword d holds k = 32h + 4t + d at position 2, 1,
-    // 0, 0 for d = 0..3.
-    for (int t = wave; t < KC * QW; t += WAVES) {
+    // The basis tiles of the group: a wave takes (kc, word q) tiles, lane t
+    // the word of B_{64kc+t}.  The basis array has n rows, so the loads go
+    // out with those of the status and the rank; rows k >= r are cleared
+    // once the rank has arrived.
+    const int status = *(volatile const int32_t *)f.status;
+    const int r = *f.rank;
+    uint64_t x[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        const int t = wave + i * WAVES;
         const int kc = t / QW, q = t - kc * QW;
         const int k = 64 * kc + lane;
-        const uint64_t x = (k < r && q < nq) ? f.basis[(size_t)k * W + w0 + q] : 0ull;
-        uint32_t y2[2] = {(uint32_t)x, (uint32_t)(x >> 32)};
+        x[i] = (k < f.n && q < nq) ? f.basis[(size_t)k * W + w0 + q] : 0ull;
+    }
+    if (status != HLF_OK) return;
+    const int KC = (r + 63) >> 6;     // K chunks of 64 = coefficient words
+    // The largest row and column weights (set bits in the group's columns)
+    // decide between the sparse path and the matrix cores; the column
+    // weights are only counted when the rows are sparse.
+    constexpr int NCOL = 64 * QW;
+    int *rowcnt = reinterpret_cast<int *>(Bop + kSpRowCnt);
+    int *colcnt = reinterpret_cast<int *>(Bop + kSpColCnt);
+    for (int k = tid; k < r; k += 64 * WAVES) rowcnt[k] = 0;
+    if (tid < NCOL) colcnt[tid] = 0;
+    if (tid < 3) Bop[kSpMaxW + tid] = 0u;
+    {   // row lists start as RMAX (the zero slice) in every entry
+        constexpr uint32_t kFill = (uint32_t)sparse_rmax<JC>() * 0x10001u;
+        for (int i = tid; i < NCOL * kSparseMaxW / 2; i += 64 * WAVES) Bop[kSpLists + i] = kFill;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        const int t = wave + i * WAVES;
+        const int k = 64 * (t / QW) + lane;
+        if (t >= KC * QW || k >= r) x[i] = 0ull;
+        if (x[i]) atomicAdd(&rowcnt[k], __popcll(x[i]));
+    }
+    __syncthreads();
+    {   // largest row weight and the K-chunk pairs in use: per wave, then one atomic
+        int wmax = 0;
+        uint32_t pm = 0u;
+        for (int k = tid; k < r; k += 64 * WAVES) {
+            const int wk = rowcnt[k];
+            wmax = max(wmax, wk);
+            pm |= wk > 0 ? 1u << (k >> 7) : 0u;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            wmax = max(wmax, __shfl_xor(wmax, off, kWave));
+            pm |= (uint32_t)__shfl_xor((int)pm, off, kWave);
+        }
+        if (lane == 0) {
+            atomicMax(reinterpret_cast<int *>(Bop + kSpMaxW), wmax);
+            atomicOr(Bop + kSpPairs, pm);
+        }
+    }
+    __syncthreads();
+    bool sparse = *(volatile int *)(Bop + kSpMaxW) <= kSparseMaxW;  // workgroup-uniform
+    if (sparse) {
+        // Row lists per column (at most kSparseMaxW kept; a longer one sends
+        // the workgroup to the matrix cores).
+        uint16_t *lists = reinterpret_cast<uint16_t *>(Bop + kSpLists);
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+            const int t = wave + i * WAVES;
+            const int kc = t / QW, q = t - kc * QW;
+            const int k = 64 * kc + lane;
+            uint64_t v = x[i];
+            while (v) {
+                const int col = 64 * q + __builtin_ctzll(v);
+                v &= v - 1;
+                const int slot = atomicAdd(&colcnt[col], 1);
+                if (slot < kSparseMaxW) lists[col * kSparseMaxW + slot] = (uint16_t)k;
+            }
+        }
+        __syncthreads();
+        int cmax = tid < NCOL ? colcnt[tid] : 0;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off, kWave));
+        if (lane == 0) atomicMax(reinterpret_cast<int *>(Bop + kSpMaxC), cmax);
+        __syncthreads();
+        const int mc = *(volatile int *)(Bop + kSpMaxC);
+        sparse = mc <= kSparseMaxW;
+        if (sparse) {
+            constexpr int RMAX = sparse_rmax<JC>();
+            if (lane == 0) Bop[kSpSlices + wave * (RMAX + 4) + RMAX] = 0u;  // the zero slice
+            if (mc <= 8) sample_sparse_blocks<JC, WAVES, 8>(f, r, seed, num, coeffs, out, Bop);
+            else sample_sparse_blocks<JC, WAVES, kSparseMaxW>(f, r, seed, num, coeffs, out, Bop);
+            return;
+        }
+    }
+    __syncthreads();  // the weights are read; the operands overwrite them
+    // B operands.  Lanes 32h .. 32h+31 of a tile hold rows 64kc + 32h +
+    // 0..31; their low dwords (columns 64q + 0..31) and high dwords (64q +
+    // 32..63), each transposed within the half, give lane (h, m) half h of
+    // column 64q + m (chunk 2q, first) and of column 64q + 32 + m (chunk
+    // 2q + 1, second).  Nibble t of dword d holds k = 32h + 4t + d at
+    // position 2, 1, 0, 0 for d = 0..3.
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        const int t = wave + i * WAVES;
+        if (t >= KC * QW) break;  // wave-uniform
+        const int kc = t / QW, q = t - kc * QW;
+        uint32_t y2[2] = {(uint32_t)x[i], (uint32_t)(x[i] >> 32)};
         half_transpose32_n<2>(y2);
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
@@ -204,8 +415,7 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
 
     uint64_t l[QW];
 #pragma unroll
-    for (int q = 0; q < QW; ++q) l[q] = q < nq ? f.shift[w0 + q] : 0ull;
-    const uint64_t lastmask = (r & 63) ? ((1ull << (r & 63)) - 1ull) : ~0ull;
+    for (int q = 0; q < QW; ++q) l[q] = uniform64(q < nq ? f.shift[w0 + q] : 0ull);  // scalar registers
     v16f magic;
 #pragma unroll
     for (int i = 0; i < 16; ++i) magic[i] = kTwo23;
@@ -229,6 +439,8 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
         constexpr bool kSeeded = decltype(seeded)::value;
         const uint64_t s = 32ull * blk + (uint64_t)m;  // this lane's A row
         const bool live = s < num;
+        // (Bits k >= r of the last word meet B operand rows k >= r, which are
+        // zero, so they need no mask.)
         // Coefficient words 2p, 2p+1 of this row are K chunks 2p, 2p+1: lane
         // half h generates word 2p+h (SplitMix64 state seed + (ctr+1) gamma,
         // advanced by 2 gamma per step).  One swap of the upper 32 lanes of
@@ -241,7 +453,6 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
             const int q = 2 * p + h;
             uint64_t mine = 0ull;
             if (live && q < KC) mine = coeffs ? coeffs[ctr0 + 2 * p] : mix13(state);
-            if (q == KC - 1) mine &= lastmask;
             state += 2 * kGamma;
             return __builtin_amdgcn_permlane32_swap((uint32_t)mine, (uint32_t)(mine >> 32), false, false);
         };

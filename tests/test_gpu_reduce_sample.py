@@ -273,3 +273,101 @@ def test_sample_matrix_core_path_gated_on_status():
     hlf.sample(F, 1, 50, out=out)
     torch.cuda.synchronize()
     assert bool((out == 0x5A5A).all())
+
+
+# --- sparse bases: the per-group choice between the sparse path and the matrix cores
+def _group_weights(Fo, words_per_group=4):
+    """Largest row and column weight of the basis within each group of 64*4
+    columns (the unit in which the sampler picks its path for W >= 4)."""
+    n, W, r = Fo["n"], Fo["words"], Fo["rank"]
+    bits = np.zeros((r, n), dtype=np.uint8)
+    for k, b in enumerate(Fo["basis"]):
+        for j in range(n):
+            bits[k, j] = (b >> j) & 1
+    out = []
+    for g0 in range(0, W, words_per_group):
+        blk = bits[:, 64 * g0: min(n, 64 * (g0 + words_per_group))]
+        out.append((int(blk.sum(axis=1).max(initial=0)), int(blk.sum(axis=0).max(initial=0))))
+    return out
+
+
+def _bounded_degree(n, deg, seed):
+    rng = np.random.default_rng(seed)
+    A = np.zeros((n, n), dtype=np.uint8)
+    d = np.zeros(n, dtype=int)
+    for _ in range(n * deg):
+        i, j = rng.integers(0, n, 2)
+        if i != j and not A[i, j] and d[i] < deg and d[j] < deg:
+            A[i, j] = A[j, i] = 1
+            d[i] += 1
+            d[j] += 1
+    A[np.arange(n), np.arange(n)] = rng.integers(0, 2, n)
+    return A
+
+
+def _mixed_sparse_dense():
+    A = np.zeros((512, 512), dtype=np.uint8)
+    A[:256, :256] = grid_instance(16, p=0.5, seed=21)
+    A[256:, 256:] = random_symmetric(256, 22, 0.5)
+    return A
+
+
+def _heavy_column(n=300, seed=23):
+    """Rows of weight <= 16 everywhere, but a column of weight about 20: the
+    last vertex is joined to the XOR of two other vertices' neighbourhoods
+    (its column depends on theirs, so it is no pivot, and the pivots next to
+    it give its basis column many set bits)."""
+    rng = np.random.default_rng(seed)
+    A = _bounded_degree(n - 1, 10, seed)
+    deg = A.sum(axis=1) - A.diagonal()
+    u, v = [int(x) for x in np.argsort(-deg)[:2]]
+    for cand in np.argsort(-deg)[1:]:
+        if not np.any(A[u, :] & A[int(cand), :]):
+            v = int(cand)
+            break
+    a = (A[:, u] ^ A[:, v]).astype(np.uint8)
+    B = np.zeros((n, n), dtype=np.uint8)
+    B[:n - 1, :n - 1] = A
+    B[n - 1, :n - 1] = a
+    B[:n - 1, n - 1] = a
+    B[n - 1, n - 1] = (a[u] ^ a[v]) & 1
+    del rng
+    return B
+
+
+@pytest.mark.parametrize("name,make,expect", [
+    ("grid 16x16 + dense 256 (sparse and matrix-core groups)", _mixed_sparse_dense, "mixed"),
+    ("degree <= 15 random, n=600", lambda: _bounded_degree(600, 15, 24), "sparse"),
+    ("degree <= 22 random, n=600", lambda: _bounded_degree(600, 22, 25), "dense"),
+    ("light rows, one heavy column, n=300", _heavy_column, "heavy column"),
+])
+def test_sample_sparse_path_choice(name, make, expect):
+    """The sampler's sparse path (rows and columns of the basis with at most
+    16 set bits in a group's columns) and its fallback to the matrix cores,
+    per group, against the oracle; the weights check that each case is built
+    as intended."""
+    A = make()
+    Fo = O.factor(A)
+    gw = _group_weights(Fo)
+    if expect == "mixed":
+        assert gw[0][0] <= 16 and gw[0][1] <= 16 and gw[1][0] > 16, gw
+    elif expect == "sparse":
+        assert all(rw <= 16 and cw <= 16 for rw, cw in gw), gw
+    elif expect == "dense":
+        assert any(rw > 16 for rw, _ in gw), gw
+    else:
+        assert all(rw <= 16 for rw, _ in gw) and any(cw > 16 for _, cw in gw), gw
+    F, st = gpu_factor(A)
+    assert st == hlf.HLF_OK and int(F.rank.item()) == Fo["rank"]
+    num = 3000
+    print(f"[sample] {name} r={Fo['rank']} weights={gw}", flush=True)
+    out = hlf.sample(F, 0xABC, num)
+    torch.cuda.synchronize()
+    assert words_to_ints(hlf.as_uint64(out).reshape(num, Fo["words"])) == O.sample(Fo, 0xABC, num)
+    R64 = (Fo["rank"] + 63) // 64
+    rng = np.random.default_rng(Fo["rank"])
+    coeffs = rng.integers(-(2**63), 2**63 - 1, size=(num, R64), dtype=np.int64)
+    out = hlf.sample(F, 0, num, coeffs=torch.from_numpy(coeffs).cuda())
+    torch.cuda.synchronize()
+    cints = words_to_ints(coeffs.view(np.uint64))
+    assert words_to_ints(hlf.as_uint64(out).reshape(num, Fo["words"])) == O.sample(Fo, 0, num, coeffs=cints)
