@@ -109,6 +109,11 @@ constexpr float kTwo23 = 8388608.0f;
 // Blocks one wave takes at most in one launch: 2^23 + 4096 * HLF_MAX_N < 2^24.
 constexpr int kMaxWaveBlocks = 4096;
 
+// a ^ b ^ c in one instruction (a three-input bitwise op, truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // 32x32 bit transposes within each half of the wave, on the VALU alone:
 // lane l of a half holds row l of each matrix and gets its column l.  Step j
 // exchanges, between lanes l and l ^ j, the bits whose row and column indices
@@ -122,22 +127,23 @@ constexpr int kMaxWaveBlocks = 4096;
 template <int N>
 __device__ __forceinline__ void half_transpose32_n(uint32_t (&x)[N]) {
     const int lane = (int)(threadIdx.x & (kWave - 1));
-    {   // j = 16
+    {   // j = 16: after the swap, the first result holds the lane's own value
+        // in rows 0 and 2 and its partner's in rows 1 and 3, the second the
+        // other way round, so one byte permute with a per-row selector merges
         const bool up = lane & 16;
-        const uint32_t sel = up ? 0x03020706u : 0x05040100u;
+        const uint32_t sel = up ? 0x07060302u : 0x05040100u;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const auto sw = __builtin_amdgcn_permlane16_swap(x[i], x[i], false, false);
-            const uint32_t y = up ? sw[0] : sw[1];
-            x[i] = __builtin_amdgcn_perm(y, x[i], sel);
+            x[i] = __builtin_amdgcn_perm(sw[1], sw[0], sel);
         }
     }
     {   // j = 8
         const uint32_t sel = (lane & 8) ? 0x03070105u : 0x06020400u;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const int t = __builtin_amdgcn_update_dpp(0, (int)x[i], 0x140, 0xF, 0xF, false);   // row mirror
-            const uint32_t y = (uint32_t)__builtin_amdgcn_update_dpp(0, t, 0x141, 0xF, 0xF, false);  // half mirror
+            const int t = __builtin_amdgcn_mov_dpp((int)x[i], 0x140, 0xF, 0xF, false);   // row mirror
+            const uint32_t y = (uint32_t)__builtin_amdgcn_mov_dpp(t, 0x141, 0xF, 0xF, false);  // half mirror
             x[i] = __builtin_amdgcn_perm(y, x[i], sel);
         }
     }
@@ -151,12 +157,12 @@ __device__ __forceinline__ void half_transpose32_n(uint32_t (&x)[N]) {
         for (int i = 0; i < N; ++i) {
             int y;
             if (j == 4) {
-                const int t = __builtin_amdgcn_update_dpp(0, (int)x[i], 0x141, 0xF, 0xF, false);  // half mirror
-                y = __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, false);                     // quad [3,2,1,0]
+                const int t = __builtin_amdgcn_mov_dpp((int)x[i], 0x141, 0xF, 0xF, false);  // half mirror
+                y = __builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, true);                     // quad [3,2,1,0]
             } else if (j == 2) {
-                y = __builtin_amdgcn_update_dpp(0, (int)x[i], 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
+                y = __builtin_amdgcn_mov_dpp((int)x[i], 0x4E, 0xF, 0xF, true);  // quad [2,3,0,1]
             } else {
-                y = __builtin_amdgcn_update_dpp(0, (int)x[i], 0xB1, 0xF, 0xF, false);  // quad [1,0,3,2]
+                y = __builtin_amdgcn_mov_dpp((int)x[i], 0xB1, 0xF, 0xF, true);  // quad [1,0,3,2]
             }
             const uint32_t t = (uint32_t)y & M;
             x[i] = (x[i] & M) | __builtin_amdgcn_alignbit(t, t, R);
@@ -175,20 +181,19 @@ __device__ __forceinline__ void half_transpose32_n(uint32_t (&x)[N]) {
 // into bit slices (slice k holds c_{s,k} of the block's 32 samples, one bit
 // per sample) in a per-wave LDS table; each output column XORs the slices of
 // the rows in its list, and the output slices are transposed back into the
-// samples' words.
+// samples' words.  The lists hold byte offsets into a wave's table, so a
+// gather is one add and one LDS read.
 // ---------------------------------------------------------------------------
 constexpr int kSparseMaxW = 16;  // set bits per basis row and column (in the group) at most
 
 // LDS layout of the sparse path, in dwords from the start of the workgroup's
 // buffer (it aliases the matrix-core operands, which are not built then).
 // RMAX bounds the rows (64 ceil(n/64)); NCOL = 64 * words per group.
-constexpr int kSpRowCnt = 0;                      // [RMAX] row weights
-constexpr int kSpMaxW = kSpRowCnt + HLF_MAX_N;    // largest row weight
-constexpr int kSpPairs = kSpMaxW + 1;             // K-chunk pairs with any set bit (mask)
-constexpr int kSpMaxC = kSpPairs + 1;             // largest column weight
-constexpr int kSpColCnt = kSpMaxC + 1;            // [NCOL] column weights
-constexpr int kSpLists = (kSpColCnt + 256 + 3) / 4 * 4;  // [NCOL][kSparseMaxW] u16 row lists (16-byte aligned)
-constexpr int kSpSlices = kSpLists + 256 * kSparseMaxW / 2;  // per wave: [RMAX + 4] slices
+constexpr int kSpVotes = 0;                       // [wave] K-chunk pairs in use << 1 | heavy word
+constexpr int kSpColVotes = 16;                   // [wave] columns above 5, 8, kSparseMaxW rows (bits 0-2)
+constexpr int kSpColCnt = 32;                     // [NCOL] column weights
+constexpr int kSpLists = kSpColCnt + 256;         // [NCOL][kSparseMaxW] row lists: 4k (16-byte aligned)
+constexpr int kSpSlices = kSpLists + 256 * kSparseMaxW;  // per wave: [RMAX + 4] slices
 static_assert(kSpLists % 4 == 0 && kSpSlices % 4 == 0, "16-byte aligned lists");
 
 // Slices per wave: every k the K-chunk pairs reach, 64 * 2 * ceil(KC/2)
@@ -198,8 +203,8 @@ constexpr int sparse_rmax() { return JC == 4 ? 256 : HLF_MAX_N; }
 
 // The 32-sample blocks of the sparse path.
 template <int JC, int WAVES, int MWB>
-__device__ __forceinline__ void sample_sparse_blocks(const FactorIn &f, int r, uint64_t seed, uint64_t num,
-                                                     const uint64_t *__restrict__ coeffs,
+__device__ __forceinline__ void sample_sparse_blocks(const FactorIn &f, int r, uint32_t pairs, uint64_t seed,
+                                                     uint64_t num, const uint64_t *__restrict__ coeffs,
                                                      uint64_t *__restrict__ out, uint32_t *lds) {
     constexpr int QW = JC / 2;
     constexpr int RMAX = sparse_rmax<JC>();
@@ -209,16 +214,41 @@ __device__ __forceinline__ void sample_sparse_blocks(const FactorIn &f, int r, u
     const int KC = (r + 63) >> 6;
     const int w0 = QW * (int)blockIdx.x;
     const int nq = min(QW, W - w0);
-    const uint32_t pairs = lds[kSpPairs];
-    const uint16_t *lists = reinterpret_cast<const uint16_t *>(lds + kSpLists);
+    const uint32_t *lists = lds + kSpLists;
     uint32_t *cs = lds + kSpSlices + wave * (RMAX + 4);  // cs[RMAX] stays zero
+    const char *csb = reinterpret_cast<const char *>(cs);
     // Lane (h, m) gathers the output columns 64c + 32h + m: their row lists
-    // (unused entries hold RMAX, the index of a zero slice) and bits of l.
+    // (unused entries point at the zero slice) and bits of l.
     uint32_t lbit[QW];
 #pragma unroll
     for (int c = 0; c < QW; ++c) {
         const uint32_t lw = c < nq ? reinterpret_cast<const uint32_t *>(f.shift)[2 * (w0 + c) + h] : 0u;
         lbit[c] = 0u - ((lw >> m) & 1u);
+    }
+    // Row lists of the lane's columns: byte offsets into the wave's table.
+    // Short lists stay in registers for the whole launch; longer ones are
+    // read per block and column.
+    constexpr bool kHoist = MWB <= 8;
+    auto load_list = [&](int c, uint32_t (&e)[MWB]) {
+        const uint32_t *lp = lists + (64 * c + 32 * h + m) * kSparseMaxW;
+#pragma unroll
+        for (int i = 0; i < MWB; i += 4) {
+            if (i + 4 <= MWB) {
+                const uint4 q4 = *reinterpret_cast<const uint4 *>(lp + i);
+                e[i] = q4.x;
+                e[i + 1] = q4.y;
+                e[i + 2] = q4.z;
+                e[i + 3] = q4.w;
+            } else {
+#pragma unroll
+                for (int j = i; j < MWB; ++j) e[j] = lp[j];
+            }
+        }
+    };
+    uint32_t kk[kHoist ? QW : 1][MWB];
+    if constexpr (kHoist) {
+#pragma unroll
+        for (int c = 0; c < QW; ++c) load_list(c, kk[c]);
     }
     uint32_t *out32 = reinterpret_cast<uint32_t *>(out);
     const uint64_t nblk = (num + 31) >> 5;
@@ -227,51 +257,46 @@ __device__ __forceinline__ void sample_sparse_blocks(const FactorIn &f, int r, u
     for (uint64_t blk = (uint64_t)blockIdx.y * per_wg + wave; blk < blk_end; blk += WAVES) {
         const uint64_t s = 32ull * blk + (uint64_t)m;  // lane (h, m): sample m of the block
         const bool live = s < num;
-        for (int p = 0; 2 * p < KC; ++p) {
+        const uint64_t ctr0 = s * (uint64_t)KC + (uint64_t)h;  // word h of the sample
+        uint64_t state = seed + (ctr0 + 1) * kGamma;  // SplitMix64 state of word 2p + h
+        for (int p = 0; 2 * p < KC; ++p, state += 2 * kGamma) {
             if (!((pairs >> p) & 1u)) continue;  // wave-uniform
             // Lane half h makes coefficient word 2p + h of its sample; within
             // each half, the low and high dwords transposed give lane (h, m)
-            // the slices of k = 64(2p+h) + m and 64(2p+h) + 32 + m.
+            // the slices of k = 64(2p+h) + m and 64(2p+h) + 32 + m.  Words of
+            // samples >= num and beyond the last one are left unmasked: they
+            // only reach bits of samples that are not stored and slices of
+            // rows >= r, which no list holds.
             const int kc = 2 * p + h;
-            const bool use = live && kc < KC;
-            const uint64_t ctr = s * (uint64_t)KC + (uint64_t)kc;
             uint64_t word;
             if (coeffs) {  // wave-uniform
-                word = use ? coeffs[ctr] : 0ull;
+                word = (live && kc < KC) ? coeffs[ctr0 + 2 * p] : 0ull;
             } else {
-                word = mix13(seed + (ctr + 1) * kGamma) & (0ull - (uint64_t)use);
+                word = mix13(state);
             }
             uint32_t y[2] = {(uint32_t)word, (uint32_t)(word >> 32)};
             half_transpose32_n<2>(y);
             cs[64 * kc + m] = y[0];
             cs[64 * kc + 32 + m] = y[1];
         }
-        // All list entries first, then all slice reads in flight together,
-        // then the XORs.
-        uint32_t kk[QW][MWB / 2];
-#pragma unroll
-        for (int c = 0; c < QW; ++c) {
-            const uint4 *lp = reinterpret_cast<const uint4 *>(lists + (64 * c + 32 * h + m) * kSparseMaxW);
-#pragma unroll
-            for (int g = 0; g < MWB / 8; ++g) {
-                const uint4 q4 = lp[g];
-                kk[c][4 * g] = q4.x;
-                kk[c][4 * g + 1] = q4.y;
-                kk[c][4 * g + 2] = q4.z;
-                kk[c][4 * g + 3] = q4.w;
-            }
-        }
-        uint32_t sv[QW][MWB];
-#pragma unroll
-        for (int c = 0; c < QW; ++c)
-#pragma unroll
-            for (int i = 0; i < MWB; ++i) sv[c][i] = cs[(kk[c][i >> 1] >> (16 * (i & 1))) & 0xFFFFu];
+        // Per column: the slices of its rows, XORed onto the bits of l.
         uint32_t v[QW];
 #pragma unroll
         for (int c = 0; c < QW; ++c) {
+            uint32_t e[MWB];
+            if constexpr (kHoist) {
+#pragma unroll
+                for (int i = 0; i < MWB; ++i) e[i] = kk[c][i];
+            } else {
+                load_list(c, e);
+            }
+            uint32_t sv[MWB];
+#pragma unroll
+            for (int i = 0; i < MWB; ++i) sv[i] = *reinterpret_cast<const uint32_t *>(csb + e[i]);
             uint32_t acc = lbit[c];
 #pragma unroll
-            for (int i = 0; i < MWB; ++i) acc ^= sv[c][i];
+            for (int i = 0; i + 1 < MWB; i += 2) acc = xor3(acc, sv[i], sv[i + 1]);
+            if (MWB & 1) acc ^= sv[MWB - 1];
             v[c] = acc;
         }
         // Slice of column 64c + 32h + m, transposed within the half: lane
@@ -293,99 +318,112 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
     __shared__ __align__(16) uint32_t Bop[kMfmaMaxKC * JC * 64 * 4];
     static_assert(kSpSlices + WAVES * (sparse_rmax<JC>() + 4) <= kMfmaMaxKC * JC * 64 * 4, "sparse layout fits");
     static_assert(64 * QW <= 256 && 64 * QW <= 64 * WAVES, "one column per thread");
+    static_assert(WAVES <= 16, "one vote word per wave");
     const int W = f.words;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, m = lane & 31;
     const int w0 = QW * (int)blockIdx.x;
     const int nq = min(QW, W - w0);   // words of this group that exist
-    // The basis tiles of the group: a wave takes (kc, word q) tiles, lane t
-    // the word of B_{64kc+t}.  The basis array has n rows, so the loads go
-    // out with those of the status and the rank; rows k >= r are cleared
-    // once the rank has arrived.
-    const int status = *(volatile const int32_t *)f.status;
+    // The group's basis words are staged in LDS ([word q][row k], at the
+    // top of the buffer): consecutive lanes load consecutive words of a row,
+    // so a row's words arrive in one request.  The basis array has n rows,
+    // so the loads go out with those of the status and the rank; rows k >= r
+    // are cleared once the rank has arrived.  (The record was written by an
+    // earlier launch: plain loads see it.)
+    constexpr int RS = sparse_rmax<JC>();  // rows staged, at most
+    constexpr int kStage = kMfmaMaxKC * JC * 64 * 4 - 2 * QW * RS;  // dwords
+    constexpr int SPT = (RS * QW + 64 * WAVES - 1) / (64 * WAVES);  // staged words per thread
+    static_assert(kSpSlices + WAVES * (RS + 4) <= kStage && kStage % 2 == 0, "staging above the sparse tables");
+    uint64_t *stage = reinterpret_cast<uint64_t *>(Bop + kStage);
+    const int status = *f.status;
     const int r = *f.rank;
-    uint64_t x[TPW];
+    {
+        uint64_t sw[SPT];
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-        const int t = wave + i * WAVES;
-        const int kc = t / QW, q = t - kc * QW;
-        const int k = 64 * kc + lane;
-        x[i] = (k < f.n && q < nq) ? f.basis[(size_t)k * W + w0 + q] : 0ull;
+        for (int i = 0; i < SPT; ++i) {
+            const int e = tid + i * 64 * WAVES;
+            const int k = e / QW, q = e % QW;
+            sw[i] = (k < f.n && q < nq) ? f.basis[(size_t)k * W + w0 + q] : 0ull;
+        }
+#pragma unroll
+        for (int i = 0; i < SPT; ++i) {
+            const int e = tid + i * 64 * WAVES;
+            if (e < RS * QW) stage[(e % QW) * RS + e / QW] = sw[i];
+        }
     }
     if (status != HLF_OK) return;
     const int KC = (r + 63) >> 6;     // K chunks of 64 = coefficient words
-    // The largest row and column weights (set bits in the group's columns)
-    // decide between the sparse path and the matrix cores; the column
-    // weights are only counted when the rows are sparse.
+    // Path choice, by votes of the waves (one LDS word per wave): the
+    // sparse path needs every basis word of the group (64 columns of a row)
+    // to have at most kSparseMaxW set bits, and then every column at most
+    // kSparseMaxW rows.
     constexpr int NCOL = 64 * QW;
-    int *rowcnt = reinterpret_cast<int *>(Bop + kSpRowCnt);
     int *colcnt = reinterpret_cast<int *>(Bop + kSpColCnt);
-    for (int k = tid; k < r; k += 64 * WAVES) rowcnt[k] = 0;
     if (tid < NCOL) colcnt[tid] = 0;
-    if (tid < 3) Bop[kSpMaxW + tid] = 0u;
     {   // row lists start as RMAX (the zero slice) in every entry
-        constexpr uint32_t kFill = (uint32_t)sparse_rmax<JC>() * 0x10001u;
-        for (int i = tid; i < NCOL * kSparseMaxW / 2; i += 64 * WAVES) Bop[kSpLists + i] = kFill;
+        constexpr uint32_t kFill = 4u * (uint32_t)sparse_rmax<JC>();
+        for (int i = tid; i < NCOL * kSparseMaxW; i += 64 * WAVES) Bop[kSpLists + i] = kFill;
     }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-        const int t = wave + i * WAVES;
-        const int k = 64 * (t / QW) + lane;
-        if (t >= KC * QW || k >= r) x[i] = 0ull;
-        if (x[i]) atomicAdd(&rowcnt[k], __popcll(x[i]));
-    }
-    __syncthreads();
-    {   // largest row weight and the K-chunk pairs in use: per wave, then one atomic
-        int wmax = 0;
-        uint32_t pm = 0u;
-        for (int k = tid; k < r; k += 64 * WAVES) {
-            const int wk = rowcnt[k];
-            wmax = max(wmax, wk);
-            pm |= wk > 0 ? 1u << (k >> 7) : 0u;
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            wmax = max(wmax, __shfl_xor(wmax, off, kWave));
-            pm |= (uint32_t)__shfl_xor((int)pm, off, kWave);
-        }
-        if (lane == 0) {
-            atomicMax(reinterpret_cast<int *>(Bop + kSpMaxW), wmax);
-            atomicOr(Bop + kSpPairs, pm);
-        }
-    }
-    __syncthreads();
-    bool sparse = *(volatile int *)(Bop + kSpMaxW) <= kSparseMaxW;  // workgroup-uniform
-    if (sparse) {
-        // Row lists per column (at most kSparseMaxW kept; a longer one sends
-        // the workgroup to the matrix cores).
-        uint16_t *lists = reinterpret_cast<uint16_t *>(Bop + kSpLists);
+    __syncthreads();  // staged words written
+    // The basis tiles: a wave takes (kc, word q) tiles, lane t the word of
+    // B_{64kc+t}.
+    uint64_t x[TPW];
+    {
+        uint32_t pm = 0u;  // K-chunk pairs with a set bit in the group's columns
+        bool heavy = false;
 #pragma unroll
         for (int i = 0; i < TPW; ++i) {
             const int t = wave + i * WAVES;
             const int kc = t / QW, q = t - kc * QW;
             const int k = 64 * kc + lane;
+            x[i] = (t < KC * QW && k < r) ? stage[q * RS + k] : 0ull;
+            if (__ballot(x[i] != 0ull)) pm |= 1u << (kc >> 1);  // kc is wave-uniform
+            heavy |= __popcll(x[i]) > kSparseMaxW;
+        }
+        const bool heavy_w = __ballot(heavy) != 0ull;
+        if (lane == 0) Bop[kSpVotes + wave] = pm << 1 | (heavy_w ? 1u : 0u);
+    }
+    __syncthreads();
+    uint32_t votes = 0u;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) votes |= Bop[kSpVotes + w];
+    votes = __builtin_amdgcn_readfirstlane(votes);  // workgroup-uniform
+    if (!(votes & 1u)) {
+        // Row lists per column (at most kSparseMaxW kept; a longer one sends
+        // the workgroup to the matrix cores).
+        uint32_t *lists = Bop + kSpLists;
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+            const int t = wave + i * WAVES;
+            const int kc = t / QW, q = t - kc * QW;
+            const uint32_t entry = 4u * (uint32_t)(64 * kc + lane);
             uint64_t v = x[i];
             while (v) {
                 const int col = 64 * q + __builtin_ctzll(v);
                 v &= v - 1;
                 const int slot = atomicAdd(&colcnt[col], 1);
-                if (slot < kSparseMaxW) lists[col * kSparseMaxW + slot] = (uint16_t)k;
+                if (slot < kSparseMaxW) lists[col * kSparseMaxW + slot] = entry;
             }
         }
         __syncthreads();
-        int cmax = tid < NCOL ? colcnt[tid] : 0;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off, kWave));
-        if (lane == 0) atomicMax(reinterpret_cast<int *>(Bop + kSpMaxC), cmax);
+        {
+            const int cw = tid < NCOL ? colcnt[tid] : 0;
+            const uint32_t cv = (__ballot(cw > 5) ? 1u : 0u) | (__ballot(cw > 8) ? 2u : 0u) |
+                                (__ballot(cw > kSparseMaxW) ? 4u : 0u);
+            if (lane == 0) Bop[kSpColVotes + wave] = cv;
+        }
         __syncthreads();
-        const int mc = *(volatile int *)(Bop + kSpMaxC);
-        sparse = mc <= kSparseMaxW;
-        if (sparse) {
+        uint32_t cf = 0u;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) cf |= Bop[kSpColVotes + w];
+        cf = __builtin_amdgcn_readfirstlane(cf);
+        if (!(cf & 4u)) {
             constexpr int RMAX = sparse_rmax<JC>();
             if (lane == 0) Bop[kSpSlices + wave * (RMAX + 4) + RMAX] = 0u;  // the zero slice
-            if (mc <= 8) sample_sparse_blocks<JC, WAVES, 8>(f, r, seed, num, coeffs, out, Bop);
-            else sample_sparse_blocks<JC, WAVES, kSparseMaxW>(f, r, seed, num, coeffs, out, Bop);
+            const uint32_t pairs = votes >> 1;
+            if (!(cf & 1u)) sample_sparse_blocks<JC, WAVES, 5>(f, r, pairs, seed, num, coeffs, out, Bop);
+            else if (!(cf & 2u)) sample_sparse_blocks<JC, WAVES, 8>(f, r, pairs, seed, num, coeffs, out, Bop);
+            else sample_sparse_blocks<JC, WAVES, kSparseMaxW>(f, r, pairs, seed, num, coeffs, out, Bop);
             return;
         }
     }
