@@ -87,16 +87,18 @@ __global__ __launch_bounds__(SampleShape<WMAX>::kThreads) void sample_kernel(
 // once, put their bits at positions 2, 1, 0, 0: every product of two set
 // bits is 1.  The product is taken as Z^T = Bm^T * C^T (the basis operand
 // first), so accumulator register i of lane l holds output bit 8*(i/4) +
-// 4*(l/32) + i%4 of the column chunk for sample l % 32: a lane assembles 16
+// 4*(l/32) + i%4 of a column chunk for sample l % 32: a lane assembles 16
 // bits of its sample's word and takes the other 16 from lane l ^ 32.
 //
-// Parity without a conversion: the first K chunk adds its products to 2^23
-// (a constant accumulator operand) instead of 0, so every sum is 2^23 + c
-// with c <= r < 2^23 the count; fp32 holds it exactly with unit spacing, so
-// bit 0 of its raw bits is bit 0 of c, the GF(2) product.  The raw bits are
-// read with __float_as_uint on each element: __builtin_bit_cast applied to
-// an element of an ext_vector_type value read element 0 for every index in
-// this compiler (the generated IR extracted lane 0 sixteen times).
+// Parity without a conversion, two chunks per accumulator: the first K chunk
+// adds its products to 2^23 (a constant accumulator operand) instead of 0,
+// and the products of the second column chunk of a pair carry the scale
+// 2^11, so every sum is 2^23 + c + 2^11 c' with c, c' <= r <= 1024 the two
+// counts.  fp32 holds it exactly (below 2^24, unit spacing), so bit 0 of its
+// raw bits is the parity of c and bit 11 that of c'.  The raw bits are read
+// with __float_as_uint on each element: __builtin_bit_cast applied to an
+// element of an ext_vector_type value read element 0 for every index in this
+// compiler (the generated IR extracted lane 0 sixteen times).
 // ---------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
@@ -105,9 +107,8 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int kMfmaMaxKC = HLF_MAX_N / 64;
 constexpr int kE2M1 = 4;         // operand format code of the instruction
 constexpr int kScaleOne = 127;   // E8M0 scale 2^0
+constexpr int kScaleHigh = 138;  // E8M0 scale 2^11
 constexpr float kTwo23 = 8388608.0f;
-// Blocks one wave takes at most in one launch: 2^23 + 4096 * HLF_MAX_N < 2^24.
-constexpr int kMaxWaveBlocks = 4096;
 
 // a ^ b ^ c in one instruction (a three-input bitwise op, truth table 0x96).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
@@ -451,30 +452,34 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
     }
     __syncthreads();
 
-    uint64_t l[QW];
+    // Lane (h, m) stores dword h of each word of sample m: chunk 2q + h.
+    uint32_t *out32 = reinterpret_cast<uint32_t *>(out);
+    uint32_t lh[QW];
 #pragma unroll
-    for (int q = 0; q < QW; ++q) l[q] = uniform64(q < nq ? f.shift[w0 + q] : 0ull);  // scalar registers
+    for (int q = 0; q < QW; ++q) {
+        const uint64_t lw = q < nq ? f.shift[w0 + q] : 0ull;
+        lh[q] = h ? (uint32_t)(lw >> 32) : (uint32_t)lw;
+    }
     v16f magic;
 #pragma unroll
     for (int i = 0; i < 16; ++i) magic[i] = kTwo23;
+    // Bit extraction (below): the parity bits of register 4t + u sit at bit 0
+    // (chunk 2q) and bit 11 (chunk 2q + 1); they go to bit 8t + 4h + u of the
+    // lane's two words.  Per u, a mask and two rotations.
+    uint32_t emask[4], erot0[4], erot1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const uint32_t sh = (uint32_t)(u + 4 * h);
+        emask[u] = 0x01010101u << sh;
+        erot0[u] = (32u - sh) & 31u;  // rotate right: bit 0 of each byte to bit sh
+        erot1[u] = (35u - sh) & 31u;  // bit 3 of each byte to bit sh
+    }
     // This workgroup's samples: a contiguous run of 32-sample blocks, taken by
     // its waves in turn (every SIMD of the CU gets the same number of blocks).
     const uint64_t nblk = (num + 31) >> 5;
     const uint64_t per_wg = (nblk + gridDim.y - 1) / gridDim.y;
     const uint64_t blk_end = min(nblk, (uint64_t)(blockIdx.y + 1) * per_wg);
-    // A wave's sums run on from one of its blocks to the next: only its first
-    // block starts from 2^23, later ones add their first K chunk to the
-    // previous block's sums.  A sum is then 2^23 plus the counts of all the
-    // wave's blocks so far (below 2^24: the launch gives a wave at most
-    // kMaxWaveBlocks blocks, of counts <= r <= HLF_MAX_N), its bit 0 the
-    // parity of that total, and a block's output bits are the XOR of its
-    // parity word and the previous one.
-    v16f acc[JC];
-    uint64_t prev[QW];
-#pragma unroll
-    for (int q = 0; q < QW; ++q) prev[q] = 0ull;
-    auto block = [&](uint64_t blk, auto seeded) {
-        constexpr bool kSeeded = decltype(seeded)::value;
+    for (uint64_t blk = (uint64_t)blockIdx.y * per_wg + wave; blk < blk_end; blk += WAVES) {
         const uint64_t s = 32ull * blk + (uint64_t)m;  // this lane's A row
         const bool live = s < num;
         // (Bits k >= r of the last word meet B operand rows k >= r, which are
@@ -494,23 +499,29 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
             state += 2 * kGamma;
             return __builtin_amdgcn_permlane32_swap((uint32_t)mine, (uint32_t)(mine >> 32), false, false);
         };
-        // The products of K chunk kc (the operands of words beyond W are zero).
+        // Accumulator q takes the products of chunk 2q with scale 1 and those
+        // of chunk 2q + 1 with scale 2^11: every sum is 2^23 + c + 2^11 c'
+        // (counts c, c' <= r <= 1024, below 2^24 and exact in fp32), so the
+        // raw bits hold the parity of c at bit 0 and that of c' at bit 11.
+        v16f acc[QW];
         auto chunk = [&](int kc, uint32_t y, bool first) {
             const v8i a = {(int)(y & 0x11111111u), (int)(y & 0x22222222u),
                            (int)(y & 0x44444444u), (int)((y >> 1) & 0x44444444u), 0, 0, 0, 0};
 #pragma unroll
-            for (int jc = 0; jc < JC; ++jc) {
-                const v4i b4 = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * JC + jc) * 64 + lane) * 4]);
-                const v8i b = {b4[0], b4[1], b4[2], b4[3], 0, 0, 0, 0};
-                acc[jc] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                    b, a, (first && kSeeded) ? magic : acc[jc], kE2M1, kE2M1, 0, kScaleOne, 0, kScaleOne);
+            for (int q = 0; q < QW; ++q) {
+                const v4i b0 = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * JC + 2 * q) * 64 + lane) * 4]);
+                const v4i b1 = *reinterpret_cast<const v4i *>(&Bop[((size_t)(kc * JC + 2 * q + 1) * 64 + lane) * 4]);
+                const v8i bl = {b0[0], b0[1], b0[2], b0[3], 0, 0, 0, 0};
+                const v8i bh = {b1[0], b1[1], b1[2], b1[3], 0, 0, 0, 0};
+                acc[q] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    bl, a, first ? magic : acc[q], kE2M1, kE2M1, 0, kScaleOne, 0, kScaleOne);
+                acc[q] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    bh, a, acc[q], kE2M1, kE2M1, 0, kScaleHigh, 0, kScaleOne);
             }
         };
         if (KC == 0) {
-            if constexpr (kSeeded) {
 #pragma unroll
-                for (int jc = 0; jc < JC; ++jc) acc[jc] = magic;
-            }
+            for (int q = 0; q < QW; ++q) acc[q] = magic;
         } else {
             auto ys = words(0);
             chunk(0, ys[0], true);
@@ -521,38 +532,30 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
                 if (2 * p + 1 < KC) chunk(2 * p + 1, ys[1], false);
             }
         }
-        // Register i holds 2^23 + the count of bit 8(i/4) + 4h + i%4: the low
-        // bytes of registers u, 4+u, 8+u, 12+u go to bytes 0..3 of one dword,
-        // whose bits 0 then move to bits 8t + u.
-        uint32_t word[JC];
-#pragma unroll
-        for (int jc = 0; jc < JC; ++jc) {
-            uint32_t c[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) c[i] = __float_as_uint(acc[jc][i]);
-            uint32_t mine = 0;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t lo = __builtin_amdgcn_perm(c[4 + u], c[u], 0x0c0c0400u);
-                const uint32_t hi = __builtin_amdgcn_perm(c[12 + u], c[8 + u], 0x04000c0cu);
-                mine |= ((lo | hi) & 0x01010101u) << u;
-            }
-            mine <<= 4 * h;
-            // lanes 0..31 (the ones that store) take the bits of lane + 32
-            word[jc] = mine | __builtin_amdgcn_permlane32_swap(mine, mine, false, false)[1];
-        }
-        const uint64_t so = 32ull * blk + (uint64_t)lane;  // row `lane` for lanes < 32
+        // Register i = 4t + u holds the bits of column 8t + 4h + u of both
+        // chunks.  Byte permutes gather bytes 0 (bit 0: chunk 2q) and 1 (bit
+        // 11 = bit 3 of byte 1: chunk 2q + 1) of registers u, 4+u, 8+u, 12+u
+        // into bytes 0..3; a rotation and a mask put each bit in place.  One
+        // swap then gives the lanes of half 0 their partner's bits of chunk 2q
+        // and those of half 1 their partner's bits of chunk 2q + 1.
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
-            const uint64_t z = ((uint64_t)word[2 * q + 1] << 32) | word[2 * q];
-            if (lane < 32 && so < num && q < nq) out[so * W + w0 + q] = z ^ prev[q] ^ l[q];
-            prev[q] = z;
+            uint32_t c[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) c[i] = __float_as_uint(acc[q][i]);
+            uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t P = __builtin_amdgcn_perm(c[4 + u], c[u], 0x05010400u);
+                const uint32_t Q = __builtin_amdgcn_perm(c[12 + u], c[8 + u], 0x05010400u);
+                const uint32_t R = __builtin_amdgcn_perm(Q, P, 0x05040100u);  // bytes 0
+                const uint32_t S = __builtin_amdgcn_perm(Q, P, 0x07060302u);  // bytes 1
+                lo |= __builtin_amdgcn_alignbit(R, R, erot0[u]) & emask[u];
+                hi |= __builtin_amdgcn_alignbit(S, S, erot1[u]) & emask[u];
+            }
+            const auto sw = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+            if (live && q < nq) out32[(s * (uint64_t)W + (uint64_t)(w0 + q)) * 2 + h] = (sw[0] | sw[1]) ^ lh[q];
         }
-    };
-    uint64_t blk = (uint64_t)blockIdx.y * per_wg + wave;
-    if (blk < blk_end) {
-        block(blk, std::true_type{});
-        for (blk += WAVES; blk < blk_end; blk += WAVES) block(blk, std::false_type{});
     }
 }
 
@@ -568,9 +571,6 @@ hlf_status launch_sample_mfma_t(const FactorIn &f, uint64_t seed, uint64_t num,
     const uint64_t most = (blocks32 + WAVES - 1) / WAVES;
     if (y > most) y = most;
     if (y == 0) y = 1;
-    // at most kMaxWaveBlocks blocks per wave (the running sums stay exact)
-    const uint64_t least = (blocks32 + (uint64_t)kMaxWaveBlocks * WAVES - 1) / ((uint64_t)kMaxWaveBlocks * WAVES);
-    if (y < least) y = least;
     if (y > 0xFFFFull) return HLF_EINVAL;
     hipLaunchKernelGGL((sample_mfma_kernel<JC, WAVES>), dim3(groups, (unsigned)y),
                        dim3(64 * WAVES), 0, stream, f, seed, num, coeffs, out);
@@ -581,7 +581,8 @@ hlf_status launch_sample_mfma(const FactorIn &f, uint64_t seed, uint64_t num,
                               const uint64_t *coeffs, uint64_t *out, hipStream_t stream) {
     // Four words (256 output bits) per workgroup from W = 4: the coefficient
     // words and A operands of a block then serve 8 products per K chunk, and
-    // 12 waves (three per SIMD, 164 VGPRs each) share the 128 KiB of operands.
+    // 12 waves (three per SIMD) share the 128 KiB of operands (four waves per
+    // SIMD measured slower).
     if (f.words >= 4) return launch_sample_mfma_t<8, 12>(f, seed, num, coeffs, out, stream);
     return launch_sample_mfma_t<4, 16>(f, seed, num, coeffs, out, stream);
 }

@@ -91,11 +91,11 @@ def test_sample_65536_n1024_every_word(name):
 
 
 def test_sample_long_runs_of_blocks():
-    """2^22 samples, so that every wave of the matrix-core kernel chains its
-    sums over many 32-sample blocks (about 85 at n = 289, 170 at n = 1024):
-    every word at n = 289 for the SplitMix64 stream, and 4096 rows spread
-    over the range at n = 1024 for explicit coefficients, against the C
-    oracle."""
+    """2^22 samples, so that every wave of the n > 192 sampler takes many
+    32-sample blocks: the sparse path on the N=17 grid (n = 289, about 85
+    blocks per wave), every word for the SplitMix64 stream; the matrix cores
+    on a dense random n = 1024 matrix (about 170 blocks per wave), 4096 rows
+    spread over the range for explicit coefficients; against the C oracle."""
     num = 1 << 22
     A = grid_instance(17, p=0.5, seed=4)
     Fo = O.factor(A)
