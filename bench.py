@@ -561,6 +561,16 @@ def serve_mode(torch):
            "saturated_requests_per_s": round(sat, 1),
            "kinds": {k: sum(1 for r in res if r.kind == k) for k in ("sample", "enumerate", "error")},
            "loads": []}
+    # Result bytes handed to the host (pinned memory) in the saturated run:
+    # every solution of an enumeration in 2-, 4- or 8-byte words (n <= 16, 32,
+    # 64), 65536 samples of ceil(n/64) words otherwise.
+    def result_bytes(r):
+        if r.kind == "enumerate":
+            return (1 << r.rank) * (2 if r.n <= 16 else 4 if r.n <= 32 else 8)
+        return 65536 * 8 * ((r.n + 63) // 64) if r.kind == "sample" else 0
+    rb = sum(result_bytes(r) for r in res)
+    out["saturated_result_bytes"] = rb
+    out["saturated_result_GB_per_s"] = round(rb * sat / count / 1e9, 2)
     for frac in (0.5, 0.8, 0.95):
         rq = reqs(frac * sat, 2)
         res = srv.run(rq, realtime=True, keep_data=False)
@@ -570,6 +580,17 @@ def serve_mode(torch):
                              "served_per_s": round(count / span, 1),
                              "p50_ms": round(percentile(lat, 50), 3),
                              "p99_ms": round(percentile(lat, 99), 3)})
+    # The host link's rate for such copies: 256 MiB device -> pinned host.
+    src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(1 << 28, dtype=torch.uint8, pin_memory=True)
+    dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(4):
+        dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    out["d2h_pinned_GB_per_s"] = round(4 * (1 << 28) / (time.perf_counter() - t0) / 1e9, 2)
+    del src, dst
     st = srv.stats()
     out["hbm_arena_bytes"] = st["hbm_bytes"]
     out["hbm_peak_bytes"] = st["hbm_peak_bytes"]
