@@ -191,7 +191,6 @@ constexpr int kSparseMaxW = 16;  // set bits per basis row and column (in the gr
 // buffer (it aliases the matrix-core operands, which are not built then).
 // RMAX bounds the rows (64 ceil(n/64)); NCOL = 64 * words per group.
 constexpr int kSpVotes = 0;                       // [wave] K-chunk pairs in use << 1 | heavy word
-constexpr int kSpColVotes = 16;                   // [wave] columns above 5, 8, kSparseMaxW rows (bits 0-2)
 constexpr int kSpColCnt = 32;                     // [NCOL] column weights
 constexpr int kSpLists = kSpColCnt + 256;         // [NCOL][kSparseMaxW] row lists: 4k (16-byte aligned)
 constexpr int kSpSlices = kSpLists + 256 * kSparseMaxW;  // per wave: [RMAX + 4] slices
@@ -407,17 +406,16 @@ __global__ __launch_bounds__(64 * WAVES) void sample_mfma_kernel(
             }
         }
         __syncthreads();
+        // Every wave reads all column weights, so all reach the same flags
+        // (columns above 5, 8, kSparseMaxW rows) without another barrier.
+        uint32_t cf;
         {
-            const int cw = tid < NCOL ? colcnt[tid] : 0;
-            const uint32_t cv = (__ballot(cw > 5) ? 1u : 0u) | (__ballot(cw > 8) ? 2u : 0u) |
-                                (__ballot(cw > kSparseMaxW) ? 4u : 0u);
-            if (lane == 0) Bop[kSpColVotes + wave] = cv;
-        }
-        __syncthreads();
-        uint32_t cf = 0u;
+            int cw = 0;
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) cf |= Bop[kSpColVotes + w];
-        cf = __builtin_amdgcn_readfirstlane(cf);
+            for (int c = lane; c < NCOL; c += 64) cw = max(cw, colcnt[c]);
+            cf = (__ballot(cw > 5) ? 1u : 0u) | (__ballot(cw > 8) ? 2u : 0u) |
+                 (__ballot(cw > kSparseMaxW) ? 4u : 0u);
+        }
         if (!(cf & 4u)) {
             constexpr int RMAX = sparse_rmax<JC>();
             if (lane == 0) Bop[kSpSlices + wave * (RMAX + 4) + RMAX] = 0u;  // the zero slice

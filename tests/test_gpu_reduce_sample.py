@@ -218,9 +218,11 @@ def test_sample_uniformity():
     ("grid N=32 all edges", grid_instance(32, p=1.0, seed=2), 129),
 ])
 def test_sample_large_n_matrix_core_path(name, A, num):
-    """n > 64 runs on the matrix cores (fp4 products, bit 0 of the fp32
-    counts): exact words against the oracle for the SplitMix64 stream and for
-    explicit coefficients, with sample counts that leave ragged blocks."""
+    """n > 64 runs on sample_mfma_kernel: the grids take its sparse path, the
+    random matrices its matrix cores (fp4 products, parities in bits 0 and 11
+    of the fp32 sums): exact words against the oracle for the SplitMix64
+    stream and for explicit coefficients, with sample counts that leave
+    ragged blocks."""
     Fo = O.factor(A)
     F, st = gpu_factor(A)
     r, W = Fo["rank"], Fo["words"]
@@ -277,8 +279,9 @@ def test_sample_matrix_core_path_gated_on_status():
 
 # --- sparse bases: the per-group choice between the sparse path and the matrix cores
 def _group_weights(Fo, words_per_group=4):
-    """Largest row and column weight of the basis within each group of 64*4
-    columns (the unit in which the sampler picks its path for W >= 4)."""
+    """Per group of 64*4 columns (the unit in which the sampler picks its path
+    for W >= 4): the largest number of set bits in one 64-column word of a
+    basis row, and the largest column weight."""
     n, W, r = Fo["n"], Fo["words"], Fo["rank"]
     bits = np.zeros((r, n), dtype=np.uint8)
     for k, b in enumerate(Fo["basis"]):
@@ -287,7 +290,9 @@ def _group_weights(Fo, words_per_group=4):
     out = []
     for g0 in range(0, W, words_per_group):
         blk = bits[:, 64 * g0: min(n, 64 * (g0 + words_per_group))]
-        out.append((int(blk.sum(axis=1).max(initial=0)), int(blk.sum(axis=0).max(initial=0))))
+        word = max(int(blk[:, 64 * w: 64 * (w + 1)].sum(axis=1).max(initial=0))
+                   for w in range((blk.shape[1] + 63) // 64))
+        out.append((word, int(blk.sum(axis=0).max(initial=0))))
     return out
 
 
@@ -336,27 +341,30 @@ def _heavy_column(n=300, seed=23):
 
 
 @pytest.mark.parametrize("name,make,expect", [
-    ("grid 16x16 + dense 256 (sparse and matrix-core groups)", _mixed_sparse_dense, "mixed"),
-    ("degree <= 15 random, n=600", lambda: _bounded_degree(600, 15, 24), "sparse"),
-    ("degree <= 22 random, n=600", lambda: _bounded_degree(600, 22, 25), "dense"),
-    ("light rows, one heavy column, n=300", _heavy_column, "heavy column"),
+    ("grid 16x16 + dense 256 (sparse and heavy-word groups)", _mixed_sparse_dense, "mixed"),
+    ("degree <= 6 random, n=600 (lists of 6-8)", lambda: _bounded_degree(600, 6, 26), "sparse 8"),
+    ("degree <= 15 random, n=600 (lists of 9-16)", lambda: _bounded_degree(600, 15, 24), "sparse 16"),
+    ("degree <= 22 random, n=600 (long lists)", lambda: _bounded_degree(600, 22, 25), "column"),
+    ("light rows, one heavy column, n=300", _heavy_column, "column"),
 ])
 def test_sample_sparse_path_choice(name, make, expect):
-    """The sampler's sparse path (rows and columns of the basis with at most
-    16 set bits in a group's columns) and its fallback to the matrix cores,
-    per group, against the oracle; the weights check that each case is built
+    """Each outcome of the sampler's per-group path choice against the
+    oracle: the sparse path when no 64-column word of a basis row has more
+    than 16 set bits and no column more than 16 rows (row lists of at most 5,
+    8 or 16 entries), the matrix cores at once for a heavy word, and after
+    the lists for a heavy column.  The weights check that each case is built
     as intended."""
     A = make()
     Fo = O.factor(A)
     gw = _group_weights(Fo)
     if expect == "mixed":
-        assert gw[0][0] <= 16 and gw[0][1] <= 16 and gw[1][0] > 16, gw
-    elif expect == "sparse":
-        assert all(rw <= 16 and cw <= 16 for rw, cw in gw), gw
-    elif expect == "dense":
-        assert any(rw > 16 for rw, _ in gw), gw
+        assert gw[0][0] <= 16 and gw[0][1] <= 5 and gw[1][0] > 16, gw
+    elif expect == "sparse 8":
+        assert all(ww <= 16 and cw <= 8 for ww, cw in gw) and any(cw > 5 for _, cw in gw), gw
+    elif expect == "sparse 16":
+        assert all(ww <= 16 and cw <= 16 for ww, cw in gw) and any(cw > 8 for _, cw in gw), gw
     else:
-        assert all(rw <= 16 for rw, _ in gw) and any(cw > 16 for _, cw in gw), gw
+        assert all(ww <= 16 for ww, _ in gw) and any(cw > 16 for _, cw in gw), gw
     F, st = gpu_factor(A)
     assert st == hlf.HLF_OK and int(F.rank.item()) == Fo["rank"]
     num = 3000
