@@ -176,8 +176,9 @@ __device__ __forceinline__ void half_transpose32_n(uint32_t (&x)[N]) {
 // basis row and every basis column has at most five set bits (a vertex and
 // its neighbours), and sampling is a sparse product: bit j of z_s is l_j XOR
 // the coefficient bits c_{s,k} of the rows k with B_k[j] = 1.  A workgroup
-// whose rows and columns have at most kSparseMaxW set bits in its columns
-// takes this path instead of the matrix cores.  Per 32-sample block, the
+// whose basis words (64 of its columns in one row) have at most kSparseMaxW
+// set bits, and whose columns have at most kSparseMaxW rows, takes this path
+// instead of the matrix cores.  Per 32-sample block, the
 // coefficient words of the K chunks that touch its columns are transposed
 // into bit slices (slice k holds c_{s,k} of the block's 32 samples, one bit
 // per sample) in a per-wave LDS table; each output column XORs the slices of
@@ -185,7 +186,7 @@ __device__ __forceinline__ void half_transpose32_n(uint32_t (&x)[N]) {
 // samples' words.  The lists hold byte offsets into a wave's table, so a
 // gather is one add and one LDS read.
 // ---------------------------------------------------------------------------
-constexpr int kSparseMaxW = 16;  // set bits per basis row and column (in the group) at most
+constexpr int kSparseMaxW = 16;  // set bits per basis word, rows per column, at most
 
 // LDS layout of the sparse path, in dwords from the start of the workgroup's
 // buffer (it aliases the matrix-core operands, which are not built then).
