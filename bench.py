@@ -346,7 +346,7 @@ def circuit_mode(hlf, torch, stream, dev):
     Fig. 1(c)) in the FPGA's counter order (Section 4): (a) the N=5 workload,
     all 2^r solutions of each of the 8 seeds as uint32, one launch per seed,
     beside the Gray-order materialise of the same instances with the same
-    launches; (b) a 32 x 32 grid subgraph with 10 edges and 4 coloured
+    launches, on one stream and on two streams in turn; (b) a 32 x 32 grid subgraph with 10 edges and 4 coloured
     vertices (n = 1024, r = 24): all 2^24 solutions as 16-word vectors."""
     from hlf_inputs import CONFIG2_SEEDS, grid_instance, sparse_grid_instance
 
@@ -369,11 +369,44 @@ def circuit_mode(hlf, torch, stream, dev):
         for F, o, rk in zip(Fs, outs, ranks):
             hlf.enumerate_solutions(F, 0, 1 << rk, 32, out=o, stream=stream)
 
+    # The same launches with the seeds dealt to two streams in turn, so that
+    # one launch's start-up and drain overlap the other's (the headline's
+    # pattern).
+    s2 = torch.cuda.Stream(device=dev)
+
+    def circ2():
+        for k, (F, r_, o, rk) in enumerate(zip(Fs, rows, outs, ranks)):
+            hlf.enumerate_circuit(F, r_, 5, 0, 1 << rk, 32, out=o, stream=stream if k % 2 == 0 else s2)
+
+    def gray2():
+        for k, (F, o, rk) in enumerate(zip(Fs, outs, ranks)):
+            hlf.enumerate_solutions(F, 0, 1 << rk, 32, out=o, stream=stream if k % 2 == 0 else s2)
+
+    def timed_two(fn, reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        joined = torch.cuda.Event()
+        fn()
+        torch.cuda.synchronize()
+        _queue_behind_spin(torch, stream, reps * 8)
+        e0.record(stream)
+        s2.wait_event(e0)
+        for _ in range(reps):
+            fn()
+        joined.record(s2)
+        stream.wait_event(joined)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
     nbytes = 4 * sum(1 << r for r in ranks)
     res = {"workload": "N=5 grid (n=25), all edges, seeds 0-7: all 2^r solutions as uint32, one launch per seed",
            "ranks": ranks, "bytes": nbytes, "kernel": "circuit_tile_kernel<uint32_t>"}
-    for name, fn in (("circuit", circ), ("gray_tile_algebra", gray)):
-        sec = _timed(torch, stream, fn, 10)
+    for name, fn, timer in (("circuit", circ, lambda f: _timed(torch, stream, f, 10)),
+                            ("gray_tile_algebra", gray, lambda f: _timed(torch, stream, f, 10)),
+                            ("circuit_two_streams", circ2, lambda f: timed_two(f, 10)),
+                            ("gray_tile_algebra_two_streams", gray2, lambda f: timed_two(f, 10))):
+        sec = timer(fn)
         res[name] = {"us": round(sec * 1e6, 2), "achieved_GBs": round(nbytes / sec / 1e9, 1),
                      "frac_of_8TBs": round(nbytes / sec / 8e12, 4),
                      "solutions_per_s_G": round(nbytes / 4 / sec / 1e9, 2)}
