@@ -45,13 +45,13 @@ REDUCE_VALU_OPS_PER_SOLUTION = 17
 REDUCE_VALU_MEASURED = {"src_sha256_16": "322899540ce79507", "ops_per_solution": 19.02}
 REDUCE_VALU_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_amd/csrc/enumerate.hip",
                        "paper_2103_00693_amd/csrc/hlf_device.h")
-# Measured: rocprofv3 --pmc SQ_INSTS_VALU over the five timed sample launches of
-# the sample mode (65536 samples of the N=32 grid, p=0.5, seed 17; the basis
-# has at most 5 set bits per row and column, so every workgroup takes the
-# sparse path): 3,354,816 wave instructions x 64 lanes / 65536 samples =
-# 3276.2 lane operations per sample.  Used while the sampler's sources are
-# the measured ones.
-SAMPLE_VALU_MEASURED = {"src_sha256_16": "f4a100c33a31eee9", "ops_per_sample": 3276.2}
+# Measured: rocprofv3 --pmc SQ_INSTS_VALU (a pass of four counters) over the
+# sample launches of the sample mode (65536 samples of the N=32 grid, p=0.5,
+# seed 17; the basis has at most 5 set bits per row and column, so every
+# workgroup takes the sparse path): 3,302,592 wave instructions x 64 lanes /
+# 65536 samples = 3225.2 lane operations per sample.  Used while the sampler's
+# sources are the measured ones.
+SAMPLE_VALU_MEASURED = {"src_sha256_16": "c9a39acb6ef60edf", "ops_per_sample": 3225.2}
 SAMPLE_VALU_SOURCES = ("paper_2103_00693_amd/csrc/sample.hip", "paper_2103_00693_amd/csrc/hlf_device.h")
 # HBM traffic of one batch_enum_kernel<uint32_t, overlap> launch of the headline step,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
