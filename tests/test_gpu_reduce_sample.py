@@ -279,9 +279,10 @@ def test_sample_matrix_core_path_gated_on_status():
 
 # --- sparse bases: the per-group choice between the sparse path and the matrix cores
 def _group_weights(Fo, words_per_group=4):
-    """Per group of 64*4 columns (the unit in which the sampler picks its path
-    for W >= 4): the largest number of set bits in one 64-column word of a
-    basis row, and the largest column weight."""
+    """Per group of 64 * words_per_group columns (the unit in which the
+    sampler picks its path: four words for W >= 4, two below): the largest
+    number of set bits in one 64-column word of a basis row, and the largest
+    column weight."""
     n, W, r = Fo["n"], Fo["words"], Fo["rank"]
     bits = np.zeros((r, n), dtype=np.uint8)
     for k, b in enumerate(Fo["basis"]):
@@ -365,10 +366,15 @@ def test_sample_sparse_path_choice(name, make, expect):
         assert all(ww <= 16 and cw <= 16 for ww, cw in gw) and any(cw > 8 for _, cw in gw), gw
     else:
         assert all(ww <= 16 for ww, _ in gw) and any(cw > 16 for _, cw in gw), gw
+    _sample_stream_and_coeffs(A, Fo, f"{name} weights={gw}")
+
+
+def _sample_stream_and_coeffs(A, Fo, label, num=3000):
+    """3000 samples (ragged last block) for the SplitMix64 stream and for
+    explicit coefficients, word for word against the oracle."""
     F, st = gpu_factor(A)
     assert st == hlf.HLF_OK and int(F.rank.item()) == Fo["rank"]
-    num = 3000
-    print(f"[sample] {name} r={Fo['rank']} weights={gw}", flush=True)
+    print(f"[sample] {label} r={Fo['rank']}", flush=True)
     out = hlf.sample(F, 0xABC, num)
     torch.cuda.synchronize()
     assert words_to_ints(hlf.as_uint64(out).reshape(num, Fo["words"])) == O.sample(Fo, 0xABC, num)
@@ -379,3 +385,23 @@ def test_sample_sparse_path_choice(name, make, expect):
     torch.cuda.synchronize()
     cints = words_to_ints(coeffs.view(np.uint64))
     assert words_to_ints(hlf.as_uint64(out).reshape(num, Fo["words"])) == O.sample(Fo, 0, num, coeffs=cints)
+
+
+@pytest.mark.parametrize("name,make,lo,hi", [
+    ("degree <= 4 random, n=190 (lists of 5)", lambda: _bounded_degree(190, 4, 34), 0, 5),
+    ("degree <= 6 random, n=150 (lists of 6-8)", lambda: _bounded_degree(150, 6, 31), 5, 8),
+    ("degree <= 15 random, n=150 (lists of 9-16)", lambda: _bounded_degree(150, 15, 32), 8, 16),
+    ("degree <= 22 random, n=100 (heavy words)", lambda: _bounded_degree(100, 22, 33), 16, None),
+])
+def test_sample_path_choice_two_word_groups(name, make, lo, hi):
+    """The same choice in the kernel for 65 <= n <= 192 (groups of two words,
+    16 waves): each list length and a heavy word, against the oracle."""
+    A = make()
+    Fo = O.factor(A)
+    assert 2 <= Fo["words"] <= 3
+    gw = _group_weights(Fo, words_per_group=2)
+    if hi is None:
+        assert any(ww > 16 for ww, _ in gw), gw
+    else:
+        assert all(ww <= 16 and cw <= hi for ww, cw in gw) and any(cw > lo for _, cw in gw), gw
+    _sample_stream_and_coeffs(A, Fo, f"{name} weights={gw}")
