@@ -51,7 +51,7 @@ REDUCE_VALU_SOURCES = ("paper_2103_00693_amd/csrc/stage2.h", "paper_2103_00693_a
 # workgroup takes the sparse path): 3,302,592 wave instructions x 64 lanes /
 # 65536 samples = 3225.2 lane operations per sample.  Used while the sampler's
 # sources are the measured ones.
-SAMPLE_VALU_MEASURED = {"src_sha256_16": "c9a39acb6ef60edf", "ops_per_sample": 3225.2}
+SAMPLE_VALU_MEASURED = {"src_sha256_16": "4c261b6ea9be0de1", "ops_per_sample": 3225.2}
 SAMPLE_VALU_SOURCES = ("paper_2103_00693_amd/csrc/sample.hip", "paper_2103_00693_amd/csrc/hlf_device.h")
 # HBM traffic of one batch_enum_kernel<uint32_t, overlap> launch of the headline step,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per

@@ -7,8 +7,8 @@
 // n <= 64 (one word): the basis (at most 64 words) is staged in LDS once per
 // workgroup; each thread produces whole samples, reading every basis row at a
 // wave-uniform address (an LDS broadcast) and applying it under a mask, so no
-// lane diverges.  Larger n run on the matrix cores (below).
-#include <type_traits>
+// lane diverges.  Larger n run in sample_mfma_kernel (below): a sparse path
+// for the sparse bases of the paper's grids, the matrix cores otherwise.
 
 #include "hlf_device.h"
 #include "hlf_internal.h"
