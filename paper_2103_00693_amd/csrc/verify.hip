@@ -133,8 +133,12 @@ __global__ __launch_bounds__(64 * kPairWaves) void pair_stats_mfma_kernel(
 // needs (lane = kernel vector), so they are encoded once into LDS without a
 // transpose.  A workgroup holds all (up to 128) of them; its 16 waves take
 // contiguous blocks of 32 strings.  The product is taken with the kernel
-// operand first, so accumulator register i of lane l holds the parity of
+// operand first, so accumulator register i of lane l holds the count of
 // kernel vector 8(i/4) + 4(l/32) + i%4 of its 32-chunk for string l % 32.
+// Two chunks share an accumulator, as in the sampler: the first K chunk adds
+// to 2^23 and the second chunk of a pair carries the scale 2^11, so a sum is
+// 2^23 + c + 2^11 c' (c, c' <= n <= 1024) and its raw bits 0 and 11 are the
+// two parities.
 constexpr int kMemMfmaMinWords = 4;
 constexpr int kMemMfmaMaxVectors = 128;
 constexpr int kMemWaves = 16;
@@ -175,12 +179,26 @@ __global__ __launch_bounds__(64 * kMemWaves) void membership_mfma_kernel(
         dst[3] = (y & 0x88888888u) >> 3;
     }
     __syncthreads();
-    uint32_t valid[JC], tgt[JC];
+    // After the extraction lane (h, m) holds the parities of chunk 2a + h
+    // for string m: its targets and valid vectors.
+    constexpr int JA = JC / 2;
+    uint32_t valid[JA], tgt[JA];
 #pragma unroll
-    for (int jc = 0; jc < JC; ++jc) {
-        const int left = nk - 32 * jc;
-        valid[jc] = left >= 32 ? ~0u : left > 0 ? (1u << left) - 1u : 0u;
-        tgt[jc] = target[jc];
+    for (int a = 0; a < JA; ++a) {
+        const int left = nk - 32 * (2 * a + h);
+        valid[a] = left >= 32 ? ~0u : left > 0 ? (1u << left) - 1u : 0u;
+        tgt[a] = target[2 * a + h];
+    }
+    m16f magic;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) magic[i] = 8388608.0f;  // 2^23
+    uint32_t emask[4], erot0[4], erot1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const uint32_t sh = (uint32_t)(u + 4 * h);
+        emask[u] = 0x01010101u << sh;
+        erot0[u] = (32u - sh) & 31u;  // rotate right: bit 0 of each byte to bit sh
+        erot1[u] = (35u - sh) & 31u;  // bit 3 of each byte to bit sh
     }
     const uint64_t nblk = (num + 31) >> 5;
     const uint64_t per_wg = (nblk + gridDim.x - 1) / gridDim.x;
@@ -198,7 +216,7 @@ __global__ __launch_bounds__(64 * kMemWaves) void membership_mfma_kernel(
             const int w = 2 * p + h;
             zw[p] = (live && w < W) ? z[s * (uint64_t)W + (uint64_t)w] : 0ull;
         }
-        m16f acc[JC];
+        m16f acc[JA];
         auto chunk = [&](int w, uint32_t y) {
             const m8i a = {(int)(y & 0x11111111u), (int)(y & 0x22222222u),
                            (int)(y & 0x44444444u), (int)((y >> 1) & 0x44444444u), 0, 0, 0, 0};
@@ -207,8 +225,12 @@ __global__ __launch_bounds__(64 * kMemWaves) void membership_mfma_kernel(
                 if (jc < jcs) {
                     const m4i b4 = *reinterpret_cast<const m4i *>(&Bop[((size_t)(w * JC + jc) * 64 + lane) * 4]);
                     const m8i b = {b4[0], b4[1], b4[2], b4[3], 0, 0, 0, 0};
-                    acc[jc] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        b, a, w == 0 ? m16f{} : acc[jc], 4, 4, 0, 127, 0, 127);
+                    const int ja = jc >> 1;
+                    if (jc & 1)
+                        acc[ja] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(b, a, acc[ja], 4, 4, 0, 138, 0, 127);
+                    else
+                        acc[ja] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            b, a, w == 0 ? magic : acc[ja], 4, 4, 0, 127, 0, 127);
                 }
             }
         };
@@ -221,29 +243,34 @@ __global__ __launch_bounds__(64 * kMemWaves) void membership_mfma_kernel(
                 if (2 * p + 1 < W) chunk(2 * p + 1, ys[1]);
             }
         }
-        // Register i holds the count of vector 8(i/4) + 4h + i%4: the low bytes
-        // of registers u, 4+u, 8+u, 12+u go to bytes 0..3 of one dword, whose
-        // bits 0 then move to bits 8t + u; lanes 0..31 take the other 16 bits
-        // from lane + 32.
+        // Register i = 4t + u holds the counts of vector 8t + 4h + u of both
+        // chunks of a pair: byte permutes gather bytes 0 (bit 0) and 1 (bit
+        // 11 = bit 3 of byte 1) of registers u, 4+u, 8+u, 12+u, a rotation and
+        // a mask put each parity at bit 8t + 4h + u, and one swap leaves lane
+        // (h, m) the 32 parities of chunk 2a + h for string m.
         uint32_t bad = 0;
 #pragma unroll
-        for (int jc = 0; jc < JC; ++jc) {
-            if (jc < jcs) {
+        for (int a = 0; a < JA; ++a) {
+            if (2 * a < jcs) {
                 uint32_t c[16];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) c[i] = (uint32_t)acc[jc][i];
-                uint32_t mine = 0;
+                for (int i = 0; i < 16; ++i) c[i] = __float_as_uint(acc[a][i]);
+                uint32_t lo = 0u, hi = 0u;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const uint32_t lo = __builtin_amdgcn_perm(c[4 + u], c[u], 0x0c0c0400u);
-                    const uint32_t hi = __builtin_amdgcn_perm(c[12 + u], c[8 + u], 0x04000c0cu);
-                    mine |= ((lo | hi) & 0x01010101u) << u;
+                    const uint32_t P = __builtin_amdgcn_perm(c[4 + u], c[u], 0x05010400u);
+                    const uint32_t Q = __builtin_amdgcn_perm(c[12 + u], c[8 + u], 0x05010400u);
+                    const uint32_t R = __builtin_amdgcn_perm(Q, P, 0x05040100u);  // bytes 0
+                    const uint32_t S = __builtin_amdgcn_perm(Q, P, 0x07060302u);  // bytes 1
+                    lo |= __builtin_amdgcn_alignbit(R, R, erot0[u]) & emask[u];
+                    hi |= __builtin_amdgcn_alignbit(S, S, erot1[u]) & emask[u];
                 }
-                mine <<= 4 * h;
-                const uint32_t word = mine | __builtin_amdgcn_permlane32_swap(mine, mine, false, false)[1];
-                bad |= (word ^ tgt[jc]) & valid[jc];
+                const auto sw = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+                bad |= ((sw[0] | sw[1]) ^ tgt[a]) & valid[a];
             }
         }
+        // lanes 0..31 (the ones that store) take the verdict of lane + 32
+        bad |= __builtin_amdgcn_permlane32_swap(bad, bad, false, false)[1];
         const uint64_t so = 32ull * blk + (uint64_t)lane;  // string `lane` for lanes < 32
         if (lane < 32 && so < num) member[so] = bad ? 0 : 1;
     }
